@@ -1,0 +1,195 @@
+"""Pins of the oracle's solvers: Algorithm 1 (red-black SOR, Sec. 5) and the
+Picard-multigrid/nonlinear-PCG solve.
+
+References: scipy's sparse direct solver on the CDA system (a special case
+that reduces to a library routine), a brute-force Picard iteration with an
+exact sparse solve per step for FLD on small grids, agreement of the two
+different iterations on the same fixed point, the closed-form CDA Green's
+function of a point source (Sec. 4.1, equation cda_greensfunction) with its
+second-order approach under grid refinement, and the discrete power balance
+at convergence.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+from synth import media
+from test_oracle_operator import assemble
+
+EPS = 1e-20
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def direct_cda(prob, h):
+    D = np.full(prob.shape, (1.0 / 3.0)) / prob.sig_hat
+    M = assemble(D, prob.sig_a, h, EPS * h).tocsc()
+    return spl.spsolve(M, prob.j.ravel() * h * h).reshape(prob.shape)
+
+
+@pytest.mark.parametrize("case", ["point", "cloud"])
+def test_cda_matches_sparse_direct_solve(oracle_mod, case):
+    if case == "point":
+        st, al, Q, h = media.point_source(12, sigma_t=10.0, albedo=0.5)
+    else:
+        st, al, Q, h = media.config("cloud128", n=16)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="cda")
+    ref = direct_cda(prob, h)
+    mg = oracle_mod.solve(prob, method="mg", tol=1e-14, max_iters=400)
+    assert mg.status == "converged"
+    assert np.linalg.norm(mg.phi - ref) <= 1e-11 * np.linalg.norm(ref)
+    if case == "point":
+        a1 = oracle_mod.solve(prob, method="alg1", tol=1e-14, max_iters=20000, check_every=25)
+        assert a1.status == "converged"
+        assert np.linalg.norm(a1.phi - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def picard_direct(oracle_mod, prob, h, iters=400, tol=1e-14):
+    """FLD fixed point by Picard iteration with an exact sparse solve each step."""
+    phi, _ = prob.init_state()
+    for _ in range(iters):
+        D = oracle_mod.limiter_pass(prob, phi)
+        M = assemble(D, prob.sig_a, h, EPS * h).tocsc()
+        new = spl.spsolve(M, prob.j.ravel() * h * h).reshape(prob.shape)
+        if np.linalg.norm(new - phi) <= tol * np.linalg.norm(new):
+            return new
+        phi = new
+    raise AssertionError("brute-force Picard did not settle")
+
+
+@pytest.mark.parametrize("case", ["point", "cloud"])
+def test_fld_fixed_point_brute_force(oracle_mod, case):
+    if case == "point":
+        st, al, Q, h = media.point_source(8, sigma_t=10.0, albedo=0.9)
+    else:
+        st, al, Q, h = media.config("cloud128", n=8)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="lp")
+    ref = picard_direct(oracle_mod, prob, h)
+    # residual floor of these systems is ~1e-13 (the reference itself sits there)
+    mg = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000)
+    assert mg.status == "converged"
+    assert np.linalg.norm(mg.phi - ref) <= 1e-10 * np.linalg.norm(ref)
+    a1 = oracle_mod.solve(prob, method="alg1", tol=1e-12, max_iters=200000, check_every=50)
+    assert a1.status == "converged"
+    assert np.linalg.norm(a1.phi - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_alg1_and_multigrid_share_the_fixed_point(oracle_mod):
+    st, al, Q, h = media.point_source(16, sigma_t=10.0, albedo=0.9)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="lp")
+    a1 = oracle_mod.solve(prob, method="alg1", tol=1e-13, max_iters=100000, check_every=20)
+    mg = oracle_mod.solve(prob, method="mg", tol=1e-13, max_iters=400)
+    assert a1.status == mg.status == "converged"
+    assert np.linalg.norm(a1.phi - mg.phi) <= 1e-10 * np.linalg.norm(mg.phi)
+
+
+def closed_form(r, sigma_t=10.0, albedo=0.9):
+    # CDA Green's function of a unit-power point source, Sec. 4.1
+    # (cda_greensfunction): phi = 3 sigma_t^2 exp(-sqrt(3(1-a)) tau) / (4 pi tau).
+    tau = sigma_t * r
+    return 3 * sigma_t ** 2 * np.exp(-np.sqrt(3 * (1 - albedo)) * tau) / (4 * np.pi * tau)
+
+
+def test_golden_closed_form_table():
+    with open(os.path.join(GOLDEN, "cda_point_source_closed_form.json")) as f:
+        g = json.load(f)
+    for r, v in zip(g["r"], g["phi"]):
+        assert closed_form(r, g["sigma_t"], g["albedo"]) == pytest.approx(v, rel=1e-14)
+
+
+def test_point_source_cda_closed_form_and_refinement(oracle_mod):
+    errs = {}
+    for n in (32, 64):
+        st, al, Q, h = media.point_source(n)
+        prob = oracle_mod.setup(st, al, Q, h, limiter="cda")
+        phi = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=400).phi
+        c = n // 2
+        for rr in (3 / 32, 4 / 32, 5 / 32, 6 / 32):
+            m = int(round(rr * n))
+            along = [phi[c + m, c, c], phi[c - m, c, c], phi[c, c + m, c], phi[c, c, c - m]]
+            errs[(n, rr)] = max(abs(v / closed_form(rr) - 1) for v in along)
+    for rr in (3 / 32, 4 / 32, 5 / 32, 6 / 32):
+        assert errs[(32, rr)] < 0.065          # 32^3: within 6.5 % for 3..6 voxels
+    # second order: the error at r = 3h(32) falls ~4x with each halving of h
+    assert errs[(64, 3 / 32)] < errs[(32, 3 / 32)] / 4.0
+
+
+def test_analytic_dirichlet_closes_the_gap(oracle_mod):
+    # Fig. 4a: with Dirichlet data from the closed form the CDA solve matches
+    # the theory better than with phi = 0 on the boundary.
+    n = 32
+    st, al, Q, h = media.point_source(n)
+    c = n // 2
+    fn = lambda I, J, K: closed_form(h * np.sqrt((I - c) ** 2 + (J - c) ** 2 + (K - c) ** 2) + 1e-300)
+    from test_oracle_operator import ghost_fill
+    g = ghost_fill(np.zeros((n, n, n)), fn)
+    zero = oracle_mod.setup(st, al, Q, h, limiter="cda")
+    exact = oracle_mod.setup(st, al, Q, h, limiter="cda", ghost_phi=g, mirror_d=True)
+    p0 = oracle_mod.solve(zero, method="alg1", tol=1e-11, max_iters=50000, check_every=50).phi
+    p1 = oracle_mod.solve(exact, method="alg1", tol=1e-11, max_iters=50000, check_every=50).phi
+    err1 = []
+    for m in range(9, 16):
+        cf = closed_form(m * h)
+        for v0, v1 in ((p0[c + m, c, c], p1[c + m, c, c]), (p0[c, c - m, c], p1[c, c - m, c])):
+            assert abs(v1 / cf - 1) < abs(v0 / cf - 1)
+            assert abs(v1 / cf - 1) < 0.011
+        err1.append(abs(p1[c + m, c, c] / cf - 1))
+    assert np.all(np.diff(err1) < 0)   # only the near-source discretisation error is left
+
+
+def test_power_balance_at_convergence(oracle_mod):
+    st, al, Q, h = media.point_source(24, sigma_t=10.0, albedo=0.9)
+    for lim in ("cda", "lp"):
+        prob = oracle_mod.setup(st, al, Q, h, limiter=lim)
+        res = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=400)
+        D = oracle_mod.limiter_pass(prob, res.phi)
+        absorbed = (prob.sig_a * res.phi).sum() * h ** 3
+        leak = 0.0
+        for ax in range(3):
+            for end in (0, -1):
+                sl = [slice(None)] * 3
+                sl[ax] = end
+                leak += (0.5 * (D[tuple(sl)] + EPS * h) * res.phi[tuple(sl)]).sum() * h
+        assert absorbed + leak == pytest.approx(1.0, rel=1e-9)   # unit emitted power
+
+
+def test_zero_emission_returns_boundary_value(oracle_mod):
+    st, al, Q, h = media.point_source(8)
+    prob = oracle_mod.setup(st, al, np.zeros_like(Q), h, phi_b=0.0)
+    for method in ("alg1", "mg"):
+        res = oracle_mod.solve(prob, method=method)
+        assert res.status == "converged" and res.rel == 0.0
+        assert np.all(res.phi == 0.0)
+
+
+def test_multigrid_levels_rule(oracle_mod):
+    lv, ok = oracle_mod.mg_levels(32, 32, 32)
+    assert ok and lv == [(32, 32, 32), (16, 16, 16), (8, 8, 8), (4, 4, 4)]
+    assert oracle_mod.mg_levels(96, 96, 96)[0][-1] == (6, 6, 6)
+    assert oracle_mod.mg_levels(160, 160, 160)[0][-1] == (5, 5, 5)
+    assert len(oracle_mod.mg_levels(512, 512, 512)[0]) == 8
+    assert not oracle_mod.mg_levels(100, 100, 100)[1]          # 25^3 coarsest > 512
+    assert oracle_mod.mg_levels(64, 32, 16)[0][-1] == (16, 8, 4)
+
+
+def test_cholesky_against_numpy(oracle_mod):
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((40, 40))
+    M = A @ A.T + 40 * np.eye(40)
+    np.testing.assert_allclose(oracle_mod.cholesky(M), np.linalg.cholesky(M), rtol=1e-12, atol=1e-13)
+    b = rng.standard_normal(40)
+    np.testing.assert_allclose(oracle_mod.cholesky_solve(M, b), np.linalg.solve(M, b), rtol=1e-11)
+
+
+def test_single_level_vcycle_is_exact(oracle_mod):
+    rng = np.random.default_rng(4)
+    n, h = 6, 1.0 / 6
+    D = rng.uniform(0.01, 3.0, (n, n, n))
+    sa = rng.uniform(0.0, 2.0, (n, n, n))
+    b = rng.standard_normal((n, n, n))
+    e = oracle_mod.linear_vcycle(D, sa, b, h, EPS * h)
+    M = assemble(D, sa, h, EPS * h).tocsc()
+    ref = spl.spsolve(M, b.ravel() * h * h).reshape(b.shape)
+    np.testing.assert_allclose(e, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
