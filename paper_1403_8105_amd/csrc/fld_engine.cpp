@@ -1,0 +1,1252 @@
+// fld_engine.cpp -- host engine and C ABI of libfld (see include/fld.h).
+//
+// One Engine drives a batch of problems (one problem = one colour channel of
+// one volume); a single-volume context is a batch of one.  Every phase of an
+// iteration is one launch over a work list that covers all unconverged
+// problems.  Memory is laid out z fastest per array; the finest level keeps
+// the FP64 state, the multigrid levels keep precision-T copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fld.h"
+#include "fld_internal.h"
+
+using namespace fld;
+
+namespace {
+
+struct DevList {
+    Task *d = nullptr;
+    int n = 0;
+};
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0;
+    long long n = 0;
+    double h = 0.0;
+    void *e = nullptr, *b = nullptr, *sa = nullptr, *f = nullptr;
+    double *band = nullptr;
+};
+
+struct Prob {
+    int vol = 0, chan = 0;
+    int nlev = 0;
+    Fine fine{};
+    Level lv[kMaxLevels];
+    std::vector<double> hist;
+    int final_k = 0;     // iteration at which the problem stopped
+    int status = FLD_OK;
+    int gid0 = 0;        // index of its finest grid in the grid table
+};
+
+struct Vol {
+    int nx, ny, nz;
+    long long n;
+    double h, sigma_eps;
+    double *sig_hat = nullptr;
+    bool has_medium = false;
+};
+
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+struct fld_engine_impl {
+    fld_options opt{};
+    bool mixed = false, mg = true;
+    size_t tsz = 8;
+    int nprob = 0;
+    std::vector<Vol> vols;
+    std::vector<Prob> probs;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<void *> allocs;
+    std::string err;
+
+    Fine *d_fines = nullptr;
+    Grid *d_grids[2] = {nullptr, nullptr};
+    int ngrids = 0;
+    DevList fine_tasks;
+    std::vector<int> fine_range;   // host copy, nprob+1
+    int *d_fine_range = nullptr;
+    DevList mid[kMaxLevels], rest[kMaxLevels], gal[kMaxLevels];
+    int *d_chol_ids[kMaxLevels] = {};
+    int n_chol[kMaxLevels] = {};
+    int max_coarse_n = 1;
+    int max_levels = 0;
+    double *d_part[4] = {};
+    double *d_scal = nullptr;
+    int *d_active = nullptr, *d_fail = nullptr;
+    std::vector<int> h_active;
+    int k_state = 0;               // next outer iteration index (resume)
+    bool solved_once = false;
+
+    // HIP-event timing of the hot kernels (options.timing)
+    struct Timed {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<Timed> timed;
+    double fine_cells = 0.0;       // sum of finest-level cells over problems
+
+    hipEvent_t next_event()
+    {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e = nullptr;
+            hipEventCreate(&e);
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    hipEvent_t tic()
+    {
+        if (!opt.timing)
+            return nullptr;
+        hipEvent_t e = next_event();
+        hipEventRecord(e, stream);
+        return e;
+    }
+    void toc(hipEvent_t a, int cls, double bytes)
+    {
+        if (!opt.timing)
+            return;
+        hipEvent_t b = next_event();
+        hipEventRecord(b, stream);
+        timed.push_back(Timed{a, b, cls, bytes});
+    }
+    // Sum the recorded intervals (after the stream was synchronised).
+    void collect_timing(double ms[4], double launches[4], double bytes[4])
+    {
+        for (int q = 0; q < 4; ++q)
+            ms[q] = launches[q] = bytes[q] = 0.0;
+        for (const Timed &t : timed) {
+            float m = 0.0f;
+            hipEventElapsedTime(&m, t.a, t.b);
+            ms[t.cls] += m;
+            launches[t.cls] += 1.0;
+            bytes[t.cls] += t.bytes;
+        }
+        timed.clear();
+        ev_used = 0;
+    }
+
+    ~fld_engine_impl()
+    {
+        if (stream)
+            hipStreamSynchronize(stream);
+        for (hipEvent_t e : ev_pool)
+            hipEventDestroy(e);
+        for (void *p : allocs)
+            hipFree(p);
+        if (own_stream && stream)
+            hipStreamDestroy(stream);
+    }
+
+    fld_status fail(fld_status s, const char *fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+
+    fld_status hip_fail(hipError_t e, const char *what)
+    {
+        if (e == hipErrorOutOfMemory)
+            return fail(FLD_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+        return fail(FLD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+
+    template <typename P>
+    fld_status dalloc(P **p, size_t bytes)
+    {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes ? bytes : 8);
+        if (e != hipSuccess)
+            return hip_fail(e, "hipMalloc");
+        allocs.push_back(q);
+        *p = (P *)q;
+        return FLD_OK;
+    }
+
+    fld_status upload_list(const std::vector<Task> &v, DevList &out)
+    {
+        out.n = (int)v.size();
+        if (v.empty())
+            return FLD_OK;
+        fld_status s = dalloc(&out.d, sizeof(Task) * v.size());
+        if (s)
+            return s;
+        hipError_t e = hipMemcpy(out.d, v.data(), sizeof(Task) * v.size(), hipMemcpyHostToDevice);
+        return e == hipSuccess ? FLD_OK : hip_fail(e, "hipMemcpy tasks");
+    }
+
+    static void add_tasks(std::vector<Task> &v, int grid, long long n)
+    {
+        for (long long s = 0; s < n; s += kTaskCells)
+            v.push_back(Task{grid, (int)std::min<long long>(kTaskCells, n - s), s});
+    }
+
+#define CK(x)                                    \
+    do {                                         \
+        fld_status s_ = (x);                     \
+        if (s_ != FLD_OK)                        \
+            return s_;                           \
+    } while (0)
+#define HK(x, what)                              \
+    do {                                         \
+        hipError_t e_ = (x);                     \
+        if (e_ != hipSuccess)                    \
+            return hip_fail(e_, what);           \
+    } while (0)
+
+    // Build every buffer and work list.  dims: per volume (nx,ny,nz); nchan
+    // problems per volume.
+    fld_status build(const fld_options &o, int nvol, const int *dims, const double *h, int nchan)
+    {
+        opt = o;
+        mixed = opt.precision == FLD_PRECISION_MIXED;
+        mg = opt.method == FLD_METHOD_MG;
+        tsz = mixed ? 4 : 8;
+        HK(hipSetDevice(opt.device), "hipSetDevice");
+        if (opt.stream) {
+            stream = (hipStream_t)opt.stream;
+        } else {
+            HK(hipStreamCreate(&stream), "hipStreamCreate");
+            own_stream = true;
+        }
+        vols.resize(nvol);
+        for (int v = 0; v < nvol; ++v) {
+            Vol &V = vols[v];
+            V.nx = dims[3 * v];
+            V.ny = dims[3 * v + 1];
+            V.nz = dims[3 * v + 2];
+            V.n = (long long)V.nx * V.ny * V.nz;
+            V.h = h[v];
+            const double L = V.h * std::max(V.nx, std::max(V.ny, V.nz));
+            V.sigma_eps = opt.sigma_eps > 0.0 ? opt.sigma_eps : 1.0e-3 / L;
+            CK(dalloc(&V.sig_hat, sizeof(double) * V.n));
+        }
+        nprob = nvol * nchan;
+        probs.resize(nprob);
+        std::vector<Fine> hf(nprob);
+        std::vector<Task> ft;
+        fine_range.assign(nprob + 1, 0);
+        for (int p = 0; p < nprob; ++p) {
+            Prob &P = probs[p];
+            P.vol = p / nchan;
+            P.chan = p % nchan;
+            const Vol &V = vols[P.vol];
+            Fine &f = P.fine;
+            f.nx = V.nx; f.ny = V.ny; f.nz = V.nz; f.prob = p; f.n = V.n;
+            f.h = V.h; f.h2 = V.h * V.h; f.eps = opt.eps; f.dghost = opt.eps * V.h;
+            f.phi_b = opt.phi_b; f.larsen_n = opt.larsen_n;
+            f.mirror = opt.boundary_d == FLD_BOUNDARY_D_MIRROR;
+            f.limiter = opt.limiter;
+            f.write_sighat = P.chan == 0;
+            f.sig_hat = V.sig_hat;
+            const size_t N8 = sizeof(double) * V.n, NT = tsz * V.n;
+            CK(dalloc(&f.sa64, N8));
+            CK(dalloc(&f.j, N8));
+            CK(dalloc(&f.phi[0], N8));
+            CK(dalloc(&f.phi[1], N8));
+            CK(dalloc(&f.D64, N8));
+            if (!mg)
+                CK(dalloc(&f.Dtmp, N8));
+            CK(dalloc(&f.b0[0], NT));
+            CK(dalloc(&f.b0[1], NT));
+            if (mg) {
+                CK(dalloc(&f.e0, NT));
+                CK(dalloc(&f.p[0], NT));
+                CK(dalloc(&f.p[1], NT));
+                if (mixed) {
+                    CK(dalloc(&f.D0, NT));
+                    CK(dalloc(&f.sa0, NT));
+                } else {
+                    f.D0 = f.D64;
+                    f.sa0 = f.sa64;
+                }
+            } else {
+                f.p[0] = f.p[1] = f.b0[1];
+                f.e0 = f.b0[1];
+            }
+            fine_range[p] = (int)ft.size();
+            fine_cells += (double)V.n;
+            add_tasks(ft, p, V.n);
+            fine_range[p + 1] = (int)ft.size();
+            hf[p] = f;
+        }
+        CK(upload_list(ft, fine_tasks));
+        CK(dalloc(&d_fine_range, sizeof(int) * (nprob + 1)));
+        HK(hipMemcpy(d_fine_range, fine_range.data(), sizeof(int) * (nprob + 1),
+                     hipMemcpyHostToDevice), "hipMemcpy");
+        CK(dalloc(&d_fines, sizeof(Fine) * nprob));
+        HK(hipMemcpy(d_fines, hf.data(), sizeof(Fine) * nprob, hipMemcpyHostToDevice), "hipMemcpy");
+        size_t maxt = std::max<size_t>(ft.size(), 1);
+        for (int q = 0; q < 4; ++q)
+            CK(dalloc(&d_part[q], sizeof(double) * maxt));
+        CK(dalloc(&d_scal, sizeof(double) * S_COUNT * nprob));
+        HK(hipMemset(d_scal, 0, sizeof(double) * S_COUNT * nprob), "hipMemset");
+        CK(dalloc(&d_active, sizeof(int) * nprob));
+        CK(dalloc(&d_fail, sizeof(int) * nprob));
+        h_active.assign(nprob, 1);
+        if (mg)
+            CK(build_hierarchy());
+        return FLD_OK;
+    }
+
+    fld_status build_hierarchy()
+    {
+        std::vector<Grid> grids[2];
+        for (int p = 0; p < nprob; ++p) {
+            Prob &P = probs[p];
+            // levels: 2:1 on all axes while every axis is even and half of it >= 4
+            int a = P.fine.nx, b = P.fine.ny, c = P.fine.nz;
+            P.nlev = 0;
+            for (;;) {
+                Level &L = P.lv[P.nlev];
+                L.nx = a; L.ny = b; L.nz = c;
+                L.n = (long long)a * b * c;
+                L.h = P.fine.h * (double)(1LL << P.nlev);
+                ++P.nlev;
+                if ((a % 2) || (b % 2) || (c % 2) || a / 2 < 4 || b / 2 < 4 || c / 2 < 4 ||
+                    P.nlev == kMaxLevels)
+                    break;
+                a /= 2; b /= 2; c /= 2;
+            }
+            max_levels = std::max(max_levels, P.nlev);
+            for (int l = 0; l < P.nlev; ++l) {
+                Level &L = P.lv[l];
+                if (l == 0) {
+                    L.e = P.fine.e0;
+                    L.b = P.fine.b0[0];
+                    L.sa = P.fine.sa0;
+                } else {
+                    CK(dalloc(&L.e, tsz * L.n));
+                    CK(dalloc(&L.b, tsz * L.n));
+                    CK(dalloc(&L.sa, tsz * L.n));
+                    CK(dalloc(&L.f, tsz * 3 * (size_t)(L.nx + 1) * (L.ny + 1) * (L.nz + 1)));
+                }
+                if (l == P.nlev - 1) {
+                    const long long W = (long long)L.ny * L.nz + 1;
+                    CK(dalloc(&L.band, sizeof(double) * L.n * W));
+                    max_coarse_n = std::max<int>(max_coarse_n, (int)L.n);
+                }
+            }
+            P.gid0 = (int)grids[0].size();
+            for (int l = 0; l < P.nlev; ++l) {
+                const Level &L = P.lv[l];
+                Grid g{};
+                g.nx = L.nx; g.ny = L.ny; g.nz = L.nz; g.prob = p; g.n = L.n;
+                g.h2 = L.h * L.h;
+                g.dghost = P.fine.dghost;
+                g.fine = l == 0;
+                g.mirror = P.fine.mirror;
+                g.finer = l > 0 ? P.gid0 + l - 1 : -1;
+                g.coarser = l + 1 < P.nlev ? P.gid0 + l + 1 : -1;
+                g.e = L.e; g.b = L.b; g.sa = L.sa; g.D = l == 0 ? P.fine.D0 : nullptr; g.f = L.f;
+                g.band = L.band;
+                grids[0].push_back(g);
+                if (l == 0)
+                    g.b = P.fine.b0[1];
+                grids[1].push_back(g);
+            }
+        }
+        ngrids = (int)grids[0].size();
+        for (int q = 0; q < 2; ++q) {
+            CK(dalloc(&d_grids[q], sizeof(Grid) * ngrids));
+            HK(hipMemcpy(d_grids[q], grids[q].data(), sizeof(Grid) * ngrids, hipMemcpyHostToDevice),
+               "hipMemcpy grids");
+        }
+        for (int l = 0; l < max_levels; ++l) {
+            std::vector<Task> m, r, g;
+            std::vector<int> ch;
+            for (int p = 0; p < nprob; ++p) {
+                const Prob &P = probs[p];
+                if (l < P.nlev - 1) {
+                    add_tasks(m, P.gid0 + l, P.lv[l].n);
+                    add_tasks(r, P.gid0 + l + 1, P.lv[l + 1].n);
+                    const Level &C = P.lv[l + 1];
+                    add_tasks(g, P.gid0 + l + 1, (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1));
+                } else if (l == P.nlev - 1) {
+                    ch.push_back(P.gid0 + l);
+                }
+            }
+            CK(upload_list(m, mid[l]));
+            CK(upload_list(r, rest[l]));
+            CK(upload_list(g, gal[l]));
+            n_chol[l] = (int)ch.size();
+            if (!ch.empty()) {
+                CK(dalloc(&d_chol_ids[l], sizeof(int) * ch.size()));
+                HK(hipMemcpy(d_chol_ids[l], ch.data(), sizeof(int) * ch.size(),
+                             hipMemcpyHostToDevice), "hipMemcpy");
+            }
+        }
+        return FLD_OK;
+    }
+
+    // ---- medium ---------------------------------------------------------
+
+    fld_status set_problem_medium(int p, const double *d_st, const double *d_al, const double *d_q)
+    {
+        Prob &P = probs[p];
+        const Vol &V = vols[P.vol];
+        DevList l;
+        // the fine list already holds exactly these tasks
+        l.d = fine_tasks.d + fine_range[p];
+        l.n = fine_range[p + 1] - fine_range[p];
+        launch_setup(stream, P.fine, l.d, l.n, d_st, d_al, d_q, V.sigma_eps, d_part[0] + fine_range[p],
+                     mixed);
+        launch_sum_partials(stream, 1, d_fine_range + p, d_part[0], d_scal + (size_t)p * S_COUNT,
+                            S_JN2, nullptr);
+        launch_after_setup(stream, 1, d_fines + p, d_scal + (size_t)p * S_COUNT);
+        HK(hipGetLastError(), "setup launch");
+        return FLD_OK;
+    }
+
+    fld_status finish_medium()
+    {
+        if (mg) {
+            for (int l = 0; l + 1 < max_levels; ++l) {
+                if (!rest[l].n)
+                    continue;
+                if (mixed)
+                    launch_mean8_sa<float>(stream, d_grids[0], rest[l].d, rest[l].n);
+                else
+                    launch_mean8_sa<double>(stream, d_grids[0], rest[l].d, rest[l].n);
+            }
+        }
+        HK(hipGetLastError(), "medium launch");
+        HK(hipStreamSynchronize(stream), "medium sync");
+        k_state = 0;
+        solved_once = false;
+        return FLD_OK;
+    }
+
+    // Validate on the device-resident copies; returns the first bad index or -1.
+    static long long first_bad(const double *st, const double *al, const double *q, long long n,
+                               int *which)
+    {
+        for (long long c = 0; c < n; ++c) {
+            if (!(std::isfinite(st[c]) && st[c] >= 0.0)) { *which = 0; return c; }
+            if (!(std::isfinite(al[c]) && al[c] >= 0.0 && al[c] <= 1.0)) { *which = 1; return c; }
+            if (!(std::isfinite(q[c]) && q[c] >= 0.0)) { *which = 2; return c; }
+        }
+        return -1;
+    }
+
+    fld_status check_host_medium(const double *st, const double *al, const double *q, long long n)
+    {
+        int which = 0;
+        const long long bad = first_bad(st, al, q, n, &which);
+        if (bad >= 0) {
+            static const char *names[3] = {"sigma_t", "albedo", "Q"};
+            const double *arr[3] = {st, al, q};
+            return fail(FLD_ERR_INVALID_ARGUMENT, "%s[%lld] = %g is out of range", names[which],
+                        bad, arr[which][bad]);
+        }
+        return FLD_OK;
+    }
+
+    // ---- multigrid cycle --------------------------------------------------
+
+    template <typename T>
+    void coarsen_and_factor()
+    {
+        Grid *G = d_grids[0];
+        for (int l = 0; l + 1 < max_levels; ++l)
+            if (gal[l].n)
+                launch_galerkin<T>(stream, G, gal[l].d, gal[l].n, d_active);
+        for (int l = 0; l < max_levels; ++l)
+            launch_chol_factor<T>(stream, G, d_chol_ids[l], n_chol[l], d_active, d_fail);
+    }
+
+    // One finest-level half-sweep moves (per cell) half of e read, all of D,
+    // half of b and sa, half of e written: 6 values of precision T.
+    template <typename T>
+    void smooth(Grid *G, int l, int colour)
+    {
+        hipEvent_t a = l == 0 ? tic() : nullptr;
+        launch_smooth<T>(stream, G, mid[l].d, mid[l].n, d_active, colour, opt.omega_s);
+        if (l == 0)
+            toc(a, 0, 3.0 * sizeof(T) * active_fine_cells());
+    }
+
+    double active_fine_cells() const
+    {
+        double c = 0.0;
+        for (int p = 0; p < nprob; ++p)
+            if (h_active[p])
+                c += (double)probs[p].fine.n;
+        return c;
+    }
+
+    template <typename T>
+    void vcycle(int par)
+    {
+        Grid *G = d_grids[par];
+        for (int l = 0; l < max_levels; ++l) {
+            if (mid[l].n) {
+                launch_zero<T>(stream, G, mid[l].d, mid[l].n, d_active);
+                for (int s = 0; s < opt.nu1; ++s) {
+                    smooth<T>(G, l, 0);
+                    smooth<T>(G, l, 1);
+                }
+                launch_restrict<T>(stream, G, rest[l].d, rest[l].n, d_active);
+            }
+            launch_chol_solve<T>(stream, G, d_chol_ids[l], n_chol[l], d_active, max_coarse_n);
+        }
+        for (int l = max_levels - 2; l >= 0; --l) {
+            if (!mid[l].n)
+                continue;
+            launch_prolong<T>(stream, G, mid[l].d, mid[l].n, d_active);
+            for (int s = 0; s < opt.nu2; ++s) {
+                smooth<T>(G, l, 1);
+                smooth<T>(G, l, 0);
+            }
+        }
+    }
+
+    double vcycle_updates() const
+    {
+        double u = 0.0;
+        for (const Prob &P : probs)
+            for (int l = 0; l + 1 < P.nlev; ++l)
+                u += (double)P.lv[l].n * (opt.nu1 + opt.nu2);
+        return u;
+    }
+
+    // ---- solves -----------------------------------------------------------
+
+    fld_status sync_active()
+    {
+        HK(hipMemcpyAsync(d_active, h_active.data(), sizeof(int) * nprob, hipMemcpyHostToDevice,
+                          stream), "active upload");
+        return FLD_OK;
+    }
+
+    fld_status read_scalars(std::vector<double> &s)
+    {
+        s.resize((size_t)S_COUNT * nprob);
+        HK(hipMemcpyAsync(s.data(), d_scal, sizeof(double) * S_COUNT * nprob,
+                          hipMemcpyDeviceToHost, stream), "scalars D2H");
+        HK(hipStreamSynchronize(stream), "sync");
+        return FLD_OK;
+    }
+
+    // Multigrid solve of every problem.  start: 0 paper init / 1 given phi
+    // already in phi[0] / 2 resume.
+    fld_status solve_mg(int start, double *updates)
+    {
+        const int N = nprob;
+        int k = 0;
+        if (start == 2) {
+            k = k_state;
+        } else {
+            if (start == 0)
+                launch_init_phi(stream, d_fines, fine_tasks.d, fine_tasks.n, d_scal, 1, mixed);
+            else
+                launch_init_phi_dirs_only();
+            for (Prob &P : probs) {
+                P.hist.clear();
+                P.status = FLD_ERR_NOT_CONVERGED;
+                P.final_k = 0;
+            }
+        }
+        std::vector<double> sc;
+        HK(hipMemsetAsync(d_fail, 0, sizeof(int) * N, stream), "memset");
+        std::fill(h_active.begin(), h_active.end(), 1);
+        CK(sync_active());
+        const int first_k = k;
+        *updates = 0.0;
+        for (;;) {
+            // D^k from phi^k; after the first iteration of this call phi^k is
+            // formed on the fly as phi^{k-1} + theta_{k-1} p^{k-1}.
+            const double cells = active_fine_cells();
+            hipEvent_t ta = tic();
+            if (k == first_k)
+                launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
+                               k & 1, k & 1, 0, 0, 0, mixed);
+            else
+                launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
+                               (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, mixed);
+            // limiter: phi and sig_hat read, D written (FP64, plus the FP32 copy in
+            // the mixed form); with the direction update also p read, phi written
+            toc(ta, 2, cells * (24.0 + (mixed ? 4.0 : 0.0) + (k == first_k ? 0.0 : tsz + 8.0)));
+            ta = tic();
+            launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, 0, k & 1,
+                            nullptr, d_part[0], mixed);
+            // residual: phi, D, sa, j read (FP64), r written in precision T
+            toc(ta, 1, cells * (32.0 + tsz));
+            launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_RES2, d_active);
+            launch_rel(stream, N, d_scal, d_active);
+            HK(hipGetLastError(), "residual launch");
+            CK(read_scalars(sc));
+            int n_active = 0;
+            for (int p = 0; p < N; ++p) {
+                if (!h_active[p])
+                    continue;
+                Prob &P = probs[p];
+                const double rel = sc[(size_t)p * S_COUNT + S_REL];
+                P.hist.push_back(rel);
+                P.final_k = k;
+                if (!std::isfinite(rel)) {
+                    P.status = FLD_ERR_DIVERGED;
+                    h_active[p] = 0;
+                } else if (rel <= opt.tol) {
+                    P.status = FLD_OK;
+                    h_active[p] = 0;
+                } else if (k - first_k >= opt.max_iters) {
+                    P.status = FLD_ERR_NOT_CONVERGED;
+                    h_active[p] = 0;
+                } else {
+                    ++n_active;
+                }
+            }
+            if (!n_active)
+                break;
+            CK(sync_active());
+            if (mixed) {
+                coarsen_and_factor<float>();
+                vcycle<float>(k & 1);
+            } else {
+                coarsen_and_factor<double>();
+                vcycle<double>(k & 1);
+            }
+            for (int p = 0; p < N; ++p)
+                if (h_active[p])
+                    for (int l = 0; l + 1 < probs[p].nlev; ++l)
+                        *updates += (double)probs[p].lv[l].n * (opt.nu1 + opt.nu2);
+            launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1,
+                             d_part[0], d_part[1], mixed);
+            launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
+            launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
+            launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0);
+            const double acells = active_fine_cells();
+            hipEvent_t td = tic();
+            launch_npcg_dir(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
+                            (k - 1) & 1, k & 1, d_part[2], d_part[3], mixed);
+            // direction: e, p_old, r (precision T) and D, sa (FP64) read, p_new written
+            toc(td, 3, acells * (16.0 + 4.0 * tsz));
+            launch_sum_partials(stream, N, d_fine_range, d_part[2], d_scal, S_RP, d_active);
+            launch_sum_partials(stream, N, d_fine_range, d_part[3], d_scal, S_PAP, d_active);
+            launch_npcg_theta(stream, N, d_scal, d_active);
+            HK(hipGetLastError(), "cycle launch");
+            ++k;
+        }
+        k_state = k;
+        return FLD_OK;
+    }
+
+    void launch_init_phi_dirs_only()
+    {
+        // phi[0] already holds the start; zero the direction/rhs ping-pongs.
+        for (Prob &P : probs) {
+            const size_t NT = tsz * P.fine.n;
+            hipMemsetAsync(P.fine.p[0], 0, NT, stream);
+            hipMemsetAsync(P.fine.p[1], 0, NT, stream);
+            hipMemsetAsync(P.fine.b0[0], 0, NT, stream);
+            hipMemsetAsync(P.fine.b0[1], 0, NT, stream);
+        }
+    }
+
+    // Algorithm 1 (single problem).  start as in solve_mg.
+    fld_status solve_alg1(int start, double *updates, double *rel_sweep)
+    {
+        Prob &P = probs[0];
+        const int every = opt.check_every > 0 ? opt.check_every : 1;
+        int it = 0;
+        if (start == 2) {
+            it = k_state;
+        } else {
+            if (start == 0)
+                launch_init_phi(stream, d_fines, fine_tasks.d, fine_tasks.n, d_scal, 0, 0);
+            else
+                launch_init_d_only();
+            P.hist.clear();
+        }
+        const int first = it;
+        std::vector<double> sc;
+        *updates = 0.0;
+        *rel_sweep = NAN;
+        bool swept = false;
+        for (;;) {
+            if ((it - first) % every == 0 || it - first == opt.max_iters) {
+                launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, nullptr, d_scal, 0, 0, 0,
+                               0, 1, 0);
+                launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, nullptr, 0, 1, 0,
+                                nullptr, d_part[0], 0);
+                launch_sum_partials(stream, 1, d_fine_range, d_part[0], d_scal, S_RES2, nullptr);
+                launch_rel(stream, 1, d_scal, nullptr);
+                HK(hipGetLastError(), "residual launch");
+                CK(read_scalars(sc));
+                const double rel = sc[S_REL];
+                P.hist.push_back(rel);
+                if (swept)
+                    *rel_sweep = std::sqrt((sc[S_SWEEP2] + sc[S_AUX]) / (double)P.fine.n) /
+                                 sc[S_JBAR];
+                if (!std::isfinite(rel)) { P.status = FLD_ERR_DIVERGED; break; }
+                if (rel <= opt.tol) { P.status = FLD_OK; break; }
+                if (it - first >= opt.max_iters) { P.status = FLD_ERR_NOT_CONVERGED; break; }
+            }
+            launch_alg1_pass(stream, d_fines, fine_tasks.d, fine_tasks.n, d_scal, 0, opt.omega,
+                             d_part[0]);
+            launch_sum_partials(stream, 1, d_fine_range, d_part[0], d_scal, S_SWEEP2, nullptr);
+            launch_alg1_pass(stream, d_fines, fine_tasks.d, fine_tasks.n, d_scal, 1, opt.omega,
+                             d_part[1]);
+            launch_sum_partials(stream, 1, d_fine_range, d_part[1], d_scal, S_AUX, nullptr);
+            *updates += (double)P.fine.n;
+            swept = true;
+            ++it;
+        }
+        P.final_k = it;
+        k_state = it;
+        return FLD_OK;
+    }
+
+    void launch_init_d_only()
+    {
+        // phi[0] holds the caller's start; D takes the paper's initial value.
+        std::vector<double> d((size_t)probs[0].fine.n, opt.eps * probs[0].fine.h);
+        hipMemcpyAsync(probs[0].fine.D64, d.data(), sizeof(double) * d.size(),
+                       hipMemcpyHostToDevice, stream);
+        hipStreamSynchronize(stream);
+    }
+
+    const double *current_phi(int p) const
+    {
+        const Prob &P = probs[p];
+        return mg ? P.fine.phi[P.final_k & 1] : P.fine.phi[0];
+    }
+
+#undef CK
+#undef HK
+};
+
+struct fld_context {
+    fld_engine_impl eng;
+    bool has_medium = false;
+};
+
+struct fld_batch {
+    fld_engine_impl eng;
+    int nvol = 0, nchan = 0;
+    std::vector<int> has_medium;
+};
+
+namespace {
+
+fld_status validate_options(const fld_options *o, std::string &err)
+{
+    if (!o) { err = "options is NULL"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->struct_size != sizeof(fld_options)) { err = "options.struct_size mismatch"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->limiter < FLD_LIMITER_CDA || o->limiter > FLD_LIMITER_LARSEN) { err = "limiter out of range"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->limiter == FLD_LIMITER_LARSEN && !(o->larsen_n > 0.0 && std::isfinite(o->larsen_n))) { err = "larsen_n must be > 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->eps > 0.0 && std::isfinite(o->eps))) { err = "eps must be > 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!std::isfinite(o->sigma_eps)) { err = "sigma_eps must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(std::isfinite(o->phi_b) && o->phi_b >= 0.0)) { err = "phi_b must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->boundary_d != FLD_BOUNDARY_D_PAPER && o->boundary_d != FLD_BOUNDARY_D_MIRROR) { err = "boundary_d out of range"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->method != FLD_METHOD_RBSOR && o->method != FLD_METHOD_MG) { err = "method out of range"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->precision != FLD_PRECISION_FP64 && o->precision != FLD_PRECISION_MIXED) { err = "precision out of range"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->method == FLD_METHOD_RBSOR && o->precision != FLD_PRECISION_FP64) { err = "Algorithm 1 runs in FP64 only"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->omega > 0.0 && o->omega < 2.0)) { err = "omega must lie in (0,2)"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->omega_s > 0.0 && o->omega_s < 2.0)) { err = "omega_s must lie in (0,2)"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 64 || o->nu2 > 64) { err = "nu1/nu2 out of range"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->max_coarsest < 1 || o->max_coarsest > 4096) { err = "max_coarsest must lie in [1,4096]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->max_iters < 0) { err = "max_iters must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->tol >= 0.0 && std::isfinite(o->tol))) { err = "tol must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->check_every < 1) { err = "check_every must be >= 1"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->device < 0) { err = "device must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    return FLD_OK;
+}
+
+fld_status validate_grid(const fld_options *o, int nx, int ny, int nz, double h, std::string &err)
+{
+    if (nx < 1 || ny < 1 || nz < 1) { err = "grid dimensions must be >= 1"; return FLD_ERR_INVALID_ARGUMENT; }
+    if ((long long)nx * ny * nz > (1LL << 31)) { err = "grid exceeds 2^31 cells"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(h > 0.0 && std::isfinite(h))) { err = "h must be finite and > 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->method == FLD_METHOD_MG) {
+        int a = nx, b = ny, c = nz;
+        while (!((a % 2) || (b % 2) || (c % 2) || a / 2 < 4 || b / 2 < 4 || c / 2 < 4)) {
+            a /= 2; b /= 2; c /= 2;
+        }
+        if ((long long)a * b * c > o->max_coarsest) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "multigrid: coarsest level %dx%dx%d exceeds max_coarsest=%d",
+                     a, b, c, o->max_coarsest);
+            err = buf;
+            return FLD_ERR_INVALID_ARGUMENT;
+        }
+    }
+    return FLD_OK;
+}
+
+void fill_report(fld_report *rep, fld_engine_impl &E, int p, int status, double ms,
+                 double updates, double rel_sweep)
+{
+    double kms[4], kl[4], kb[4];
+    E.collect_timing(kms, kl, kb);
+    if (!rep || rep->struct_size != sizeof(fld_report))
+        return;
+    double tb = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        rep->kernel_ms[q] = kms[q];
+        rep->kernel_launches[q] = kl[q];
+        rep->kernel_bytes[q] = kb[q];
+        tb += kb[q];
+    }
+    const auto &P = E.probs[p];
+    rep->status = status;
+    rep->iterations = P.final_k;
+    rep->rel = P.hist.empty() ? NAN : P.hist.back();
+    rep->rel_sweep = rel_sweep;
+    rep->history_len = (int)P.hist.size();
+    if (rep->history && rep->history_cap > 0)
+        for (int q = 0; q < std::min<int>(rep->history_cap, (int)P.hist.size()); ++q)
+            rep->history[q] = P.hist[q];
+    rep->time_ms = ms;
+    rep->voxel_updates = updates;
+    rep->bytes = tb;
+}
+
+}  // namespace
+
+extern "C" {
+
+fld_status fld_default_options(fld_options *o)
+{
+    if (!o)
+        return FLD_ERR_INVALID_ARGUMENT;
+    memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(fld_options);
+    o->limiter = FLD_LIMITER_LP;
+    o->larsen_n = 2.0;
+    o->eps = 1e-20;
+    o->sigma_eps = -1.0;
+    o->phi_b = 0.0;
+    o->boundary_d = FLD_BOUNDARY_D_PAPER;
+    o->method = FLD_METHOD_MG;
+    o->precision = FLD_PRECISION_FP64;
+    o->omega = 1.0;
+    o->omega_s = 1.0;
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->max_coarsest = 512;
+    o->max_iters = 10000;
+    o->tol = 1e-6;
+    o->check_every = 1;
+    o->device = 0;
+    o->stream = nullptr;
+    o->timing = 0;
+    return FLD_OK;
+}
+
+static thread_local std::string g_create_err;
+
+fld_status fld_create(const fld_options *o, int nx, int ny, int nz, double h, fld_context **out)
+{
+    if (!out)
+        return FLD_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    std::string err;
+    fld_status s = validate_options(o, err);
+    if (s == FLD_OK)
+        s = validate_grid(o, nx, ny, nz, h, err);
+    if (s != FLD_OK) {
+        g_create_err = err;
+        return s;
+    }
+    fld_context *c = new (std::nothrow) fld_context;
+    if (!c)
+        return FLD_ERR_OUT_OF_MEMORY;
+    int dims[3] = {nx, ny, nz};
+    s = c->eng.build(*o, 1, dims, &h, 1);
+    if (s != FLD_OK) {
+        g_create_err = c->eng.err;
+        delete c;
+        return s;
+    }
+    *out = c;
+    return FLD_OK;
+}
+
+static fld_status set_medium_impl(fld_context *c, const double *st, const double *al,
+                                  const double *q, bool device, void *hs)
+{
+    if (!c)
+        return FLD_ERR_INVALID_ARGUMENT;
+    if (!st || !al || !q)
+        return c->eng.fail(FLD_ERR_INVALID_ARGUMENT, "medium pointer is NULL");
+    auto &E = c->eng;
+    const long long n = E.vols[0].n;
+    if (hs && hs != E.stream) {
+        // order the caller's stream before ours
+        hipEvent_t ev;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return E.fail(FLD_ERR_DEVICE, "hipEventCreate failed");
+        hipEventRecord(ev, (hipStream_t)hs);
+        hipStreamWaitEvent(E.stream, ev, 0);
+        hipEventDestroy(ev);
+    }
+    std::vector<double> hst, hal, hq;
+    const double *pst = st, *pal = al, *pq = q;
+    if (device) {
+        hst.resize(n); hal.resize(n); hq.resize(n);
+        if (hipMemcpyAsync(hst.data(), st, 8 * n, hipMemcpyDeviceToHost, E.stream) != hipSuccess ||
+            hipMemcpyAsync(hal.data(), al, 8 * n, hipMemcpyDeviceToHost, E.stream) != hipSuccess ||
+            hipMemcpyAsync(hq.data(), q, 8 * n, hipMemcpyDeviceToHost, E.stream) != hipSuccess ||
+            hipStreamSynchronize(E.stream) != hipSuccess)
+            return E.fail(FLD_ERR_DEVICE, "reading device medium failed");
+        pst = hst.data(); pal = hal.data(); pq = hq.data();
+    }
+    fld_status s = E.check_host_medium(pst, pal, pq, n);
+    if (s != FLD_OK)
+        return s;
+    double *dst = nullptr, *dal = nullptr, *dq = nullptr;
+    const double *ust = st, *ual = al, *uq = q;
+    if (!device) {
+        if (hipMalloc(&dst, 8 * n) != hipSuccess || hipMalloc(&dal, 8 * n) != hipSuccess ||
+            hipMalloc(&dq, 8 * n) != hipSuccess) {
+            hipFree(dst); hipFree(dal); hipFree(dq);
+            return E.fail(FLD_ERR_OUT_OF_MEMORY, "staging allocation failed");
+        }
+        hipMemcpyAsync(dst, st, 8 * n, hipMemcpyHostToDevice, E.stream);
+        hipMemcpyAsync(dal, al, 8 * n, hipMemcpyHostToDevice, E.stream);
+        hipMemcpyAsync(dq, q, 8 * n, hipMemcpyHostToDevice, E.stream);
+        ust = dst; ual = dal; uq = dq;
+    }
+    s = E.set_problem_medium(0, ust, ual, uq);
+    if (s == FLD_OK)
+        s = E.finish_medium();
+    if (!device) {
+        hipFree(dst); hipFree(dal); hipFree(dq);
+    }
+    if (s == FLD_OK)
+        c->has_medium = true;
+    return s;
+}
+
+fld_status fld_set_medium(fld_context *c, const double *sigma_t, const double *albedo,
+                          const double *Q)
+{
+    return set_medium_impl(c, sigma_t, albedo, Q, false, nullptr);
+}
+
+fld_status fld_set_medium_device(fld_context *c, const double *d_sigma_t, const double *d_albedo,
+                                 const double *d_Q, void *hip_stream)
+{
+    return set_medium_impl(c, d_sigma_t, d_albedo, d_Q, true, hip_stream);
+}
+
+static fld_status solve_impl(fld_context *c, const double *phi_init, bool init_device,
+                             double *phi_out, bool out_device, int resume, fld_report *rep)
+{
+    if (!c)
+        return FLD_ERR_INVALID_ARGUMENT;
+    auto &E = c->eng;
+    if (!c->has_medium)
+        return E.fail(FLD_ERR_STATE, "fld_solve before a medium was set");
+    if (resume && !E.solved_once)
+        return E.fail(FLD_ERR_STATE, "resume before any solve");
+    const long long n = E.vols[0].n;
+    std::vector<double> sc;
+    auto t0 = std::chrono::steady_clock::now();
+    fld_status s = E.read_scalars(sc);
+    if (s != FLD_OK)
+        return s;
+    if (sc[S_JN2] == 0.0) {
+        // No emission: the fluence is the boundary value (nothing to solve).
+        std::vector<double> v((size_t)n, E.opt.phi_b);
+        if (phi_out) {
+            hipError_t e = hipMemcpy(phi_out, v.data(), 8 * n,
+                                     out_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost);
+            if (e != hipSuccess)
+                return E.hip_fail(e, "phi_out copy");
+        }
+        hipMemcpy(E.probs[0].fine.phi[0], v.data(), 8 * n, hipMemcpyHostToDevice);
+        E.probs[0].final_k = 0;
+        E.probs[0].hist.assign(1, 0.0);
+        E.solved_once = true;
+        fill_report(rep, E, 0, FLD_OK, 0.0, 0.0, NAN);
+        return FLD_OK;
+    }
+    int start = resume ? 2 : (phi_init ? 1 : 0);
+    if (start == 1) {
+        hipError_t e = hipMemcpyAsync(E.probs[0].fine.phi[0], phi_init, 8 * n,
+                                      init_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                      E.stream);
+        if (e != hipSuccess)
+            return E.hip_fail(e, "phi_init copy");
+    }
+    double updates = 0.0, rel_sweep = NAN;
+    s = E.mg ? E.solve_mg(start, &updates) : E.solve_alg1(start, &updates, &rel_sweep);
+    if (s != FLD_OK)
+        return s;
+    E.solved_once = true;
+    if (phi_out) {
+        hipError_t e = hipMemcpyAsync(phi_out, E.current_phi(0), 8 * n,
+                                      out_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                      E.stream);
+        if (e != hipSuccess)
+            return E.hip_fail(e, "phi_out copy");
+    }
+    hipError_t e = hipStreamSynchronize(E.stream);
+    if (e != hipSuccess)
+        return E.hip_fail(e, "solve sync");
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const int st = E.probs[0].status;
+    fill_report(rep, E, 0, st, ms, updates, rel_sweep);
+    if (st == FLD_ERR_NOT_CONVERGED)
+        E.fail(FLD_ERR_NOT_CONVERGED, "not converged after %d iterations (rel %g)",
+               E.probs[0].final_k, E.probs[0].hist.empty() ? NAN : E.probs[0].hist.back());
+    if (st == FLD_ERR_DIVERGED)
+        E.fail(FLD_ERR_DIVERGED, "residual became non-finite at iteration %d", E.probs[0].final_k);
+    return (fld_status)st;
+}
+
+fld_status fld_solve(fld_context *c, const double *phi_init, double *phi_out, fld_report *rep)
+{
+    return solve_impl(c, phi_init, false, phi_out, false, 0, rep);
+}
+
+fld_status fld_solve_device(fld_context *c, const double *d_phi_init, double *d_phi_out,
+                            int resume, fld_report *rep)
+{
+    return solve_impl(c, d_phi_init, true, d_phi_out, true, resume, rep);
+}
+
+fld_status fld_solve_resume(fld_context *c, double *phi_out, fld_report *rep)
+{
+    return solve_impl(c, nullptr, false, phi_out, false, 1, rep);
+}
+
+static fld_status residual_impl(fld_context *c, const double *phi, bool dev, double *r_out,
+                                double *rel_out)
+{
+    if (!c)
+        return FLD_ERR_INVALID_ARGUMENT;
+    auto &E = c->eng;
+    if (!c->has_medium)
+        return E.fail(FLD_ERR_STATE, "fld_residual before a medium was set");
+    if (!rel_out)
+        return E.fail(FLD_ERR_INVALID_ARGUMENT, "rel_out is NULL");
+    const long long n = E.vols[0].n;
+    Fine f = E.probs[0].fine;
+    double *tphi = nullptr, *tD = nullptr, *tr = nullptr;
+    void *tb = nullptr;
+    Fine *dfine = nullptr;
+    auto cleanup = [&]() { hipFree(tphi); hipFree(tD); hipFree(tr); hipFree(tb); hipFree(dfine); };
+    if (hipMalloc(&tphi, 8 * n) != hipSuccess || hipMalloc(&tD, 8 * n) != hipSuccess ||
+        hipMalloc(&tr, 8 * n) != hipSuccess || hipMalloc(&tb, 8 * n) != hipSuccess ||
+        hipMalloc(&dfine, sizeof(Fine)) != hipSuccess) {
+        cleanup();
+        return E.fail(FLD_ERR_OUT_OF_MEMORY, "residual scratch allocation failed");
+    }
+    const double *src = phi ? phi : E.current_phi(0);
+    hipMemcpyAsync(tphi, src, 8 * n,
+                   (phi && !dev) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, E.stream);
+    f.phi[0] = f.phi[1] = tphi;
+    f.Dtmp = tD;
+    f.b0[0] = f.b0[1] = tb;
+    hipMemcpyAsync(dfine, &f, sizeof(Fine), hipMemcpyHostToDevice, E.stream);
+    launch_limiter(E.stream, dfine, E.fine_tasks.d, E.fine_tasks.n, nullptr, E.d_scal, 0, 0, 0, 0,
+                   1, 0);
+    launch_residual(E.stream, dfine, E.fine_tasks.d, E.fine_tasks.n, nullptr, 0, 1, 0, tr,
+                    E.d_part[0], 0);
+    launch_sum_partials(E.stream, 1, E.d_fine_range, E.d_part[0], E.d_scal, S_AUX, nullptr);
+    std::vector<double> sc;
+    fld_status s = E.read_scalars(sc);
+    if (s == FLD_OK) {
+        *rel_out = sc[S_JNORM] > 0.0 ? std::sqrt(sc[S_AUX]) / sc[S_JNORM] : 0.0;
+        if (r_out) {
+            hipError_t e = hipMemcpy(r_out, tr, 8 * n, dev ? hipMemcpyDeviceToDevice
+                                                            : hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                s = E.hip_fail(e, "r_out copy");
+        }
+    }
+    hipStreamSynchronize(E.stream);
+    cleanup();
+    return s;
+}
+
+fld_status fld_residual(fld_context *c, const double *phi, double *r_out, double *rel_out)
+{
+    return residual_impl(c, phi, false, r_out, rel_out);
+}
+
+fld_status fld_residual_device(fld_context *c, const double *d_phi, double *d_r_out,
+                               double *rel_out)
+{
+    return residual_impl(c, d_phi, true, d_r_out, rel_out);
+}
+
+void fld_destroy(fld_context *c) { delete c; }
+
+const char *fld_status_string(fld_status s)
+{
+    switch (s) {
+    case FLD_OK: return "ok";
+    case FLD_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case FLD_ERR_OUT_OF_MEMORY: return "out of memory";
+    case FLD_ERR_DEVICE: return "device error";
+    case FLD_ERR_NOT_CONVERGED: return "not converged";
+    case FLD_ERR_DIVERGED: return "diverged";
+    case FLD_ERR_STATE: return "invalid call order";
+    }
+    return "unknown status";
+}
+
+const char *fld_last_error(const fld_context *c)
+{
+    if (!c)
+        return g_create_err.empty() ? "invalid context" : g_create_err.c_str();
+    return c->eng.err.c_str();
+}
+
+// ---- batch ------------------------------------------------------------------
+
+fld_status fld_batch_create(const fld_options *o, int nvol, const int *dims3, const double *h,
+                            int nchan, fld_batch **out)
+{
+    if (!out)
+        return FLD_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    std::string err;
+    if (nvol < 1 || nchan < 1 || !dims3 || !h) {
+        g_create_err = "batch: nvol/nchan must be >= 1 and dims3/h non-NULL";
+        return FLD_ERR_INVALID_ARGUMENT;
+    }
+    fld_status s = validate_options(o, err);
+    if (s == FLD_OK && o->method != FLD_METHOD_MG) {
+        err = "batched solves use the multigrid method";
+        s = FLD_ERR_INVALID_ARGUMENT;
+    }
+    for (int v = 0; s == FLD_OK && v < nvol; ++v)
+        s = validate_grid(o, dims3[3 * v], dims3[3 * v + 1], dims3[3 * v + 2], h[v], err);
+    if (s != FLD_OK) {
+        g_create_err = err;
+        return s;
+    }
+    fld_batch *b = new (std::nothrow) fld_batch;
+    if (!b)
+        return FLD_ERR_OUT_OF_MEMORY;
+    s = b->eng.build(*o, nvol, dims3, h, nchan);
+    if (s != FLD_OK) {
+        g_create_err = b->eng.err;
+        delete b;
+        return s;
+    }
+    b->nvol = nvol;
+    b->nchan = nchan;
+    b->has_medium.assign(nvol, 0);
+    *out = b;
+    return FLD_OK;
+}
+
+fld_status fld_batch_set_volume(fld_batch *b, int v, const double *sigma_t,
+                                const double *const *albedo, const double *const *Q)
+{
+    if (!b)
+        return FLD_ERR_INVALID_ARGUMENT;
+    auto &E = b->eng;
+    if (v < 0 || v >= b->nvol || !sigma_t || !albedo || !Q)
+        return E.fail(FLD_ERR_INVALID_ARGUMENT, "bad volume index or NULL pointer");
+    const long long n = E.vols[v].n;
+    for (int ch = 0; ch < b->nchan; ++ch) {
+        if (!albedo[ch] || !Q[ch])
+            return E.fail(FLD_ERR_INVALID_ARGUMENT, "channel %d pointer is NULL", ch);
+        fld_status s = E.check_host_medium(sigma_t, albedo[ch], Q[ch], n);
+        if (s != FLD_OK)
+            return s;
+    }
+    double *dst = nullptr, *dal = nullptr, *dq = nullptr;
+    if (hipMalloc(&dst, 8 * n) != hipSuccess || hipMalloc(&dal, 8 * n) != hipSuccess ||
+        hipMalloc(&dq, 8 * n) != hipSuccess) {
+        hipFree(dst); hipFree(dal); hipFree(dq);
+        return E.fail(FLD_ERR_OUT_OF_MEMORY, "staging allocation failed");
+    }
+    hipMemcpyAsync(dst, sigma_t, 8 * n, hipMemcpyHostToDevice, E.stream);
+    fld_status s = FLD_OK;
+    for (int ch = 0; ch < b->nchan && s == FLD_OK; ++ch) {
+        hipMemcpyAsync(dal, albedo[ch], 8 * n, hipMemcpyHostToDevice, E.stream);
+        hipMemcpyAsync(dq, Q[ch], 8 * n, hipMemcpyHostToDevice, E.stream);
+        s = E.set_problem_medium(v * b->nchan + ch, dst, dal, dq);
+        hipStreamSynchronize(E.stream);
+    }
+    hipFree(dst); hipFree(dal); hipFree(dq);
+    if (s != FLD_OK)
+        return s;
+    b->has_medium[v] = 1;
+    for (int q = 0; q < b->nvol; ++q)
+        if (!b->has_medium[q])
+            return FLD_OK;
+    return E.finish_medium();
+}
+
+fld_status fld_batch_solve(fld_batch *b, double *const *phi_out, int *iters_out, fld_report *rep)
+{
+    if (!b)
+        return FLD_ERR_INVALID_ARGUMENT;
+    auto &E = b->eng;
+    for (int q = 0; q < b->nvol; ++q)
+        if (!b->has_medium[q])
+            return E.fail(FLD_ERR_STATE, "volume %d has no medium", q);
+    auto t0 = std::chrono::steady_clock::now();
+    double updates = 0.0;
+    fld_status s = E.solve_mg(0, &updates);
+    if (s != FLD_OK)
+        return s;
+    E.solved_once = true;
+    if (phi_out)
+        for (int p = 0; p < E.nprob; ++p)
+            if (phi_out[p]) {
+                hipError_t e = hipMemcpyAsync(phi_out[p], E.current_phi(p),
+                                              8 * E.vols[E.probs[p].vol].n, hipMemcpyDeviceToHost,
+                                              E.stream);
+                if (e != hipSuccess)
+                    return E.hip_fail(e, "phi_out copy");
+            }
+    hipError_t e = hipStreamSynchronize(E.stream);
+    if (e != hipSuccess)
+        return E.hip_fail(e, "batch sync");
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    int worst = 0, status = FLD_OK;
+    for (int p = 0; p < E.nprob; ++p) {
+        if (iters_out)
+            iters_out[p] = E.probs[p].final_k;
+        if (E.probs[p].final_k > E.probs[worst].final_k)
+            worst = p;
+        if (E.probs[p].status != FLD_OK && status == FLD_OK)
+            status = E.probs[p].status;
+    }
+    fill_report(rep, E, worst, status, ms, updates, NAN);
+    return (fld_status)status;
+}
+
+void fld_batch_destroy(fld_batch *b) { delete b; }
+
+const char *fld_batch_last_error(const fld_batch *b)
+{
+    if (!b)
+        return g_create_err.empty() ? "invalid batch" : g_create_err.c_str();
+    return b->eng.err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// fld_internal.h -- device-side descriptors shared by the HIP kernels and the
+// host engine of libfld.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fld {
+
+constexpr int kBlock = 256;          // threads per block of the work-list kernels
+constexpr int kTaskCells = 4096;     // cells per work-list task
+constexpr int kMaxLevels = 16;
+
+// One multigrid level of one problem.  Arrays are z fastest,
+// index (i*ny + j)*nz + k.  The finest level keeps cell coefficients D (its
+// face coefficients follow the discretised equation, (D_p + D_s)/2 with the
+// ghost rule); coarse levels keep Galerkin face coefficients f: three
+// (nx+1)(ny+1)(nz+1) arrays back to back, f[a](i,j,k) = face below (i,j,k)
+// along axis a.
+struct Grid {
+    int nx, ny, nz, prob;
+    long long n;
+    double h2;       // h_l^2
+    double dghost;   // ghost coefficient of the finest level (eps*h)
+    int fine;        // 1: cell D, 0: face arrays
+    int mirror;      // finest level: ghost D = D of the voxel inside
+    int finer;       // index of the next finer grid in the same table (-1: none)
+    int coarser;     // index of the next coarser grid (-1: none)
+    void *e, *b, *sa, *D, *f;
+    double *band;    // coarsest level: banded Cholesky factor of h^2 A, n*(ny*nz+1)
+};
+
+// A contiguous run of cells [start, start+count) of grid `grid`.
+struct Task {
+    int grid;
+    int count;
+    long long start;
+};
+
+// Finest-level FP64 state of one problem (one colour channel of one volume).
+struct Fine {
+    int nx, ny, nz, prob;
+    long long n;
+    double h, h2, dghost, eps, phi_b, larsen_n;
+    int mirror, limiter, write_sighat, pad;
+    double *sig_hat, *sa64, *j;
+    double *phi[2];      // fluence ping-pong: phi^k lives in phi[k & 1]
+    double *D64;         // limiter output (multigrid) / Algorithm 1 state D
+    double *Dtmp;        // Algorithm 1: D of the true-residual check
+    void *b0[2];         // V-cycle right-hand side ping-pong (precision T)
+    void *e0;            // finest correction (precision T)
+    void *p[2];          // search-direction ping-pong (precision T)
+    void *D0, *sa0;      // finest coefficients in precision T
+};
+
+// Per-problem device scalars.
+enum Scalar {
+    S_JN2 = 0, S_JBAR, S_JNORM, S_RES2, S_REL, S_GAMMA, S_GAMMA_PREV, S_SIGMA, S_RP, S_PAP,
+    S_BETA, S_THETA, S_SWEEP2, S_AUX, S_COUNT
+};
+
+enum Limiter { L_CDA = 0, L_LP = 1, L_SUM = 2, L_MAX = 3, L_KERSHAW = 4, L_LARSEN = 5 };
+
+// ---- launchers (fld_kernels.hip) ----------------------------------------
+// Every launcher enqueues on `s`; tasks/grids/fines are device pointers.
+// `active` (device, per problem, may be null) masks converged problems.
+
+// Algorithm 1 set-up for one problem: sig_hat = max(sigma_t, sigma_eps)
+// (written when f.write_sighat), sa = (1 - albedo) sig_hat, j = Q, partial
+// sums of Q^2 per task.
+void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
+                  const double *sigma_t, const double *albedo, const double *Q,
+                  double sigma_eps, double *partials, int mixed);
+void launch_sum_partials(hipStream_t s, int nprob, const int *range, const double *partials,
+                         double *scal, int slot, const int *active);
+void launch_after_setup(hipStream_t s, int nprob, const Fine *fines, double *scal);
+void launch_init_phi(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                     const double *scal, int zero_dirs, int mixed);
+void launch_limiter(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                    const int *active, const double *scal, int src, int dst, int use_dir,
+                    int dir_idx, int to_tmp, int mixed);
+void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                     const int *active, int src, int use_tmp, int b0_idx, double *r_out,
+                     double *partials, int mixed);
+void launch_rel(hipStream_t s, int nprob, double *scal, const int *active);
+void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const int *active, int b0_idx, double *pg, double *ps, int mixed);
+void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first);
+void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                     const int *active, const double *scal, int b0_idx, int pin, int pout,
+                     double *prp, double *ppap, int mixed);
+void launch_npcg_theta(hipStream_t s, int nprob, double *scal, const int *active);
+void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const double *scal, int colour, double omega, double *partials);
+
+// Multigrid level kernels, precision T = float (mixed) or double.  `grids`
+// is the device table of every level of every problem; a task names the grid
+// it works on (for restriction and Galerkin coarsening: the coarse grid, for
+// prolongation: the fine grid).
+template <typename T>
+void launch_zero(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                 const int *active);
+template <typename T>
+void launch_smooth(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                   const int *active, int colour, double omega);
+template <typename T>
+void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                     const int *active);
+template <typename T>
+void launch_prolong(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                    const int *active);
+template <typename T>
+void launch_galerkin(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                     const int *active);
+template <typename T>
+void launch_mean8_sa(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks);
+// Coarsest level: one block per listed grid.  fail[prob] is set to 1 when a
+// pivot is not positive.
+template <typename T>
+void launch_chol_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
+                        const int *active, int *fail);
+template <typename T>
+void launch_chol_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
+                       const int *active, int max_n);
+
+}  // namespace fld

@@ -1,0 +1,1025 @@
+// fld_kernels.hip -- HIP kernels of the flux-limited diffusion solve (gfx950).
+//
+// Work-list kernels: every launch walks a device table of tasks (runs of
+// cells of one grid of one problem), so one launch serves one volume or a
+// whole batch of volumes and colour channels.  Blocks stride over the task
+// list; a task of a converged problem is skipped.  Reductions are
+// deterministic: each task writes one partial sum, and partials are summed
+// per problem in task order.
+//
+// Arithmetic follows the discretised equations of the paper (Sec. 5) in a
+// fixed order (neighbours x-, x+, y-, y+, z-, z+), compiled without
+// floating-point contraction so FP64 results match a plain scalar reference
+// up to the rounding of library functions.
+#include <hip/hip_runtime.h>
+
+#include "fld_internal.h"
+
+namespace fld {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ inline void decode(long long c, int ny, int nz, int &i, int &j, int &k)
+{
+    long long row = c / nz;
+    k = (int)(c - row * nz);
+    i = (int)(row / ny);
+    j = (int)(row - (long long)i * ny);
+}
+
+// Sum of v over the block; the result is valid in thread 0.
+__device__ double block_sum(double v)
+{
+    __shared__ double ws[kBlock / kWave];
+    for (int o = kWave / 2; o > 0; o >>= 1)
+        v += __shfl_down(v, o, kWave);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0)
+        ws[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kBlock / kWave; ++q)
+            t += ws[q];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Flux limiters F(R), Sec. 4 Table 2.
+// ---------------------------------------------------------------------------
+
+// Levermore-Pomraning (coth R - 1/R)/R.  For R < 2 the subtraction cancels;
+// there the value comes from the continued fraction of coth (Lambert):
+// coth R - 1/R = R/(3 + R^2/(5 + R^2/(7 + ...))), cut at the partial
+// denominator 25.  Above, coth R = 1 + 2/expm1(2R).
+__device__ inline double limiter_lp(double R)
+{
+    if (R < 2.0) {
+        const double x = R * R;
+        double t = 25.0;
+#pragma unroll
+        for (int m = 11; m >= 1; --m)
+            t = (double)(2 * m + 1) + x / t;
+        return 1.0 / t;
+    }
+    const double coth = 1.0 + 2.0 / expm1(2.0 * R);
+    return (coth - 1.0 / R) / R;
+}
+
+__device__ inline double limiter(int kind, double R, double n)
+{
+    switch (kind) {
+    case L_CDA:
+        return 1.0 / 3.0;
+    case L_LP:
+        return limiter_lp(R);
+    case L_SUM:
+        return 1.0 / (3.0 + R);
+    case L_MAX:
+        return 1.0 / fmax(3.0, R);
+    case L_KERSHAW:
+        return 2.0 / (3.0 + sqrt(9.0 + 4.0 * R * R));
+    default:  // Larsen-n, written so R^n cannot overflow
+        if (R <= 3.0)
+            return pow(pow(3.0, n) + pow(R, n), -1.0 / n);
+        return (1.0 / R) * pow(1.0 + pow(3.0 / R, n), -1.0 / n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finest level (FP64 state)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock)
+k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const double *albedo,
+        const double *Q, double sigma_eps, double *partials, float *sa32)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            const double sh = fmax(sigma_t[c], sigma_eps);
+            if (f.write_sighat)
+                f.sig_hat[c] = sh;
+            const double sa = (1.0 - albedo[c]) * sh;
+            f.sa64[c] = sa;
+            if (sa32)
+                sa32[c] = (float)sa;
+            const double jq = Q[c];
+            f.j[c] = jq;
+            acc += jq * jq;
+        }
+        acc = block_sum(acc);
+        if (threadIdx.x == 0)
+            partials[t] = acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_init_phi(const Fine *fines, const Task *tasks, int ntasks, const double *scal, int zero_dirs)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        const double v = f.eps * scal[f.prob * S_COUNT + S_JBAR] * f.h;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            f.phi[0][c] = v;
+            if (f.Dtmp)
+                f.D64[c] = f.eps * f.h;
+            if (zero_dirs) {
+                ((T *)f.p[0])[c] = (T)0;
+                ((T *)f.p[1])[c] = (T)0;
+                ((T *)f.b0[0])[c] = (T)0;
+                ((T *)f.b0[1])[c] = (T)0;
+            }
+        }
+    }
+}
+
+// Limiter pass: (optionally) phi <- phi + theta*p, then for every voxel the
+// central-difference gradient, the guarded Knudsen number and
+// D = F(R)/sig_hat (Sec. 5: grad_approx, knudsen_numerical, D_update).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, const double *scal,
+          int src, int dst, int use_dir, int dir_idx, int to_tmp)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        if (active && !active[f.prob])
+            continue;
+        const double *phi = f.phi[src];
+        const T *dir = (const T *)f.p[dir_idx];
+        const double theta = use_dir ? scal[f.prob * S_COUNT + S_THETA] : 0.0;
+        const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
+        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
+        double *Dout = to_tmp ? f.Dtmp : f.D64;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, f.ny, f.nz, i, j, k);
+            auto val = [&](long long x) {
+                double v = phi[x];
+                if (use_dir)
+                    v = v + theta * (double)dir[x];
+                return v;
+            };
+            const double pc = val(c);
+            const double xm = i > 0 ? val(c - sx) : f.phi_b;
+            const double xp = i < f.nx - 1 ? val(c + sx) : f.phi_b;
+            const double ym = j > 0 ? val(c - sy) : f.phi_b;
+            const double yp = j < f.ny - 1 ? val(c + sy) : f.phi_b;
+            const double zm = k > 0 ? val(c - 1) : f.phi_b;
+            const double zp = k < f.nz - 1 ? val(c + 1) : f.phi_b;
+            const double dx = xp - xm, dy = yp - ym, dz = zp - zm;
+            const double grad = sqrt(dx * dx + dy * dy + dz * dz) / (2.0 * f.h);
+            const double sh = f.sig_hat[c];
+            const double R = fmax(grad, floor_) / fmax(sh * pc, floor_);
+            const double D = limiter(f.limiter, R, f.larsen_n) / sh;
+            Dout[c] = D;
+            if (!to_tmp && sizeof(T) == 4)
+                ((float *)f.D0)[c] = (float)D;
+            if (use_dir && dst != src)
+                f.phi[dst][c] = pc;
+        }
+    }
+}
+
+// Residual of the discretised equation (LHS - RHS, Sec. 5 R_calc):
+// r = (num - phi*den)/h^2, num = j h^2 + sum_s D_ps phi_s,
+// den = sa h^2 + sum_s D_ps, D_ps = (D_p + D_s)/2.  Writes r in precision T
+// as the V-cycle right-hand side and per-task partial sums of r^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, int src,
+           int use_tmp, int b0_idx, double *r_out, double *partials)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        if (active && !active[f.prob]) {
+            if (threadIdx.x == 0)
+                partials[t] = 0.0;
+            continue;
+        }
+        const double *phi = f.phi[src];
+        const double *D = use_tmp ? f.Dtmp : f.D64;
+        T *b0 = (T *)f.b0[b0_idx];
+        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, f.ny, f.nz, i, j, k);
+            const double Dc = D[c];
+            const double gD = f.mirror ? Dc : f.dghost;
+            double num = f.j[c] * f.h2;
+            double den = f.sa64[c] * f.h2;
+            double F;
+            F = 0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
+            num = num + F * (i > 0 ? phi[c - sx] : f.phi_b);
+            den = den + F;
+            F = 0.5 * (Dc + (i < f.nx - 1 ? D[c + sx] : gD));
+            num = num + F * (i < f.nx - 1 ? phi[c + sx] : f.phi_b);
+            den = den + F;
+            F = 0.5 * (Dc + (j > 0 ? D[c - sy] : gD));
+            num = num + F * (j > 0 ? phi[c - sy] : f.phi_b);
+            den = den + F;
+            F = 0.5 * (Dc + (j < f.ny - 1 ? D[c + sy] : gD));
+            num = num + F * (j < f.ny - 1 ? phi[c + sy] : f.phi_b);
+            den = den + F;
+            F = 0.5 * (Dc + (k > 0 ? D[c - 1] : gD));
+            num = num + F * (k > 0 ? phi[c - 1] : f.phi_b);
+            den = den + F;
+            F = 0.5 * (Dc + (k < f.nz - 1 ? D[c + 1] : gD));
+            num = num + F * (k < f.nz - 1 ? phi[c + 1] : f.phi_b);
+            den = den + F;
+            const double r = (num - phi[c] * den) / f.h2;
+            b0[c] = (T)r;
+            if (r_out)
+                r_out[c] = r;
+            acc += r * r;
+        }
+        acc = block_sum(acc);
+        if (threadIdx.x == 0)
+            partials[t] = acc;
+    }
+}
+
+// gamma = b0 . e and sigma = e . b0_prev (conjugate-gradient coefficients).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
+            double *pg, double *ps)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        if (active && !active[f.prob])
+            continue;
+        const T *b = (const T *)f.b0[b0_idx];
+        const T *bp = (const T *)f.b0[b0_idx ^ 1];
+        const T *e = (const T *)f.e0;
+        double g = 0.0, sg = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            const double ev = (double)e[c];
+            g += (double)b[c] * ev;
+            sg += ev * (double)bp[c];
+        }
+        g = block_sum(g);
+        sg = block_sum(sg);
+        if (threadIdx.x == 0) {
+            pg[t] = g;
+            ps[t] = sg;
+        }
+    }
+}
+
+// p_new = e + beta p_old (stored in precision T) and the partial sums of
+// r . p_new and p_new . A(D) p_new with the FP64 finest operator
+// (A x)_c = (x_c den - sum_s D_ps x_s)/h^2, zero ghosts.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, const double *scal,
+           int b0_idx, int pin, int pout, double *prp, double *ppap)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        if (active && !active[f.prob])
+            continue;
+        const T *e = (const T *)f.e0;
+        const T *po = (const T *)f.p[pin];
+        T *pn = (T *)f.p[pout];
+        const T *b = (const T *)f.b0[b0_idx];
+        const double *D = f.D64;
+        const double beta = scal[f.prob * S_COUNT + S_BETA];
+        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
+        double arp = 0.0, apap = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, f.ny, f.nz, i, j, k);
+            auto pv = [&](long long x) { return (double)(T)((double)e[x] + beta * (double)po[x]); };
+            const double Dc = D[c];
+            const double gD = f.mirror ? Dc : f.dghost;
+            const double pc = pv(c);
+            double nb = 0.0;
+            double den = f.sa64[c] * f.h2;
+            double F;
+            F = 0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
+            nb = nb + F * (i > 0 ? pv(c - sx) : 0.0);
+            den = den + F;
+            F = 0.5 * (Dc + (i < f.nx - 1 ? D[c + sx] : gD));
+            nb = nb + F * (i < f.nx - 1 ? pv(c + sx) : 0.0);
+            den = den + F;
+            F = 0.5 * (Dc + (j > 0 ? D[c - sy] : gD));
+            nb = nb + F * (j > 0 ? pv(c - sy) : 0.0);
+            den = den + F;
+            F = 0.5 * (Dc + (j < f.ny - 1 ? D[c + sy] : gD));
+            nb = nb + F * (j < f.ny - 1 ? pv(c + sy) : 0.0);
+            den = den + F;
+            F = 0.5 * (Dc + (k > 0 ? D[c - 1] : gD));
+            nb = nb + F * (k > 0 ? pv(c - 1) : 0.0);
+            den = den + F;
+            F = 0.5 * (Dc + (k < f.nz - 1 ? D[c + 1] : gD));
+            nb = nb + F * (k < f.nz - 1 ? pv(c + 1) : 0.0);
+            den = den + F;
+            const double Ap = (pc * den - nb) / f.h2;
+            pn[c] = (T)pc;
+            arp += (double)b[c] * pc;
+            apap += pc * Ap;
+        }
+        arp = block_sum(arp);
+        apap = block_sum(apap);
+        if (threadIdx.x == 0) {
+            prp[t] = arp;
+            ppap[t] = apap;
+        }
+    }
+}
+
+// Algorithm 1, one colour: per voxel Knudsen number from the current
+// fluence, D_p update, face coefficients with the neighbours' stored D,
+// residual with the pre-update phi_p, SOR blend of numerator/denominator.
+// Voxels of one colour only read the other colour, so the pass is in place.
+__global__ void __launch_bounds__(kBlock)
+k_alg1_pass(const Fine *fines, const Task *tasks, int ntasks, const double *scal, int colour,
+            double omega, double *partials)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        double *phi = f.phi[0];
+        double *D = f.D64;
+        const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
+        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, f.ny, f.nz, i, j, k);
+            if (((i + j + k) & 1) != colour)
+                continue;
+            const double pc = phi[c];
+            const double xm = i > 0 ? phi[c - sx] : f.phi_b;
+            const double xp = i < f.nx - 1 ? phi[c + sx] : f.phi_b;
+            const double ym = j > 0 ? phi[c - sy] : f.phi_b;
+            const double yp = j < f.ny - 1 ? phi[c + sy] : f.phi_b;
+            const double zm = k > 0 ? phi[c - 1] : f.phi_b;
+            const double zp = k < f.nz - 1 ? phi[c + 1] : f.phi_b;
+            const double dx = xp - xm, dy = yp - ym, dz = zp - zm;
+            const double grad = sqrt(dx * dx + dy * dy + dz * dz) / (2.0 * f.h);
+            const double sh = f.sig_hat[c];
+            const double R = fmax(grad, floor_) / fmax(sh * pc, floor_);
+            const double Dc = limiter(f.limiter, R, f.larsen_n) / sh;
+            D[c] = Dc;
+            const double gD = f.mirror ? Dc : f.dghost;
+            double num = f.j[c] * f.h2;
+            double den = f.sa64[c] * f.h2;
+            double F;
+            F = 0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
+            num = num + F * xm;
+            den = den + F;
+            F = 0.5 * (Dc + (i < f.nx - 1 ? D[c + sx] : gD));
+            num = num + F * xp;
+            den = den + F;
+            F = 0.5 * (Dc + (j > 0 ? D[c - sy] : gD));
+            num = num + F * ym;
+            den = den + F;
+            F = 0.5 * (Dc + (j < f.ny - 1 ? D[c + sy] : gD));
+            num = num + F * yp;
+            den = den + F;
+            F = 0.5 * (Dc + (k > 0 ? D[c - 1] : gD));
+            num = num + F * zm;
+            den = den + F;
+            F = 0.5 * (Dc + (k < f.nz - 1 ? D[c + 1] : gD));
+            num = num + F * zp;
+            den = den + F;
+            const double Rp = (num - pc * den) / f.h2;
+            phi[c] = omega * (num / den) + (1.0 - omega) * pc;
+            acc += Rp * Rp;
+        }
+        acc = block_sum(acc);
+        if (threadIdx.x == 0)
+            partials[t] = acc;
+    }
+}
+
+// Per-problem sum of task partials, range[p] .. range[p+1].
+__global__ void __launch_bounds__(kBlock)
+k_sum_partials(const int *range, const double *partials, double *scal, int slot, const int *active)
+{
+    const int p = blockIdx.x;
+    if (active && !active[p])
+        return;
+    double acc = 0.0;
+    for (int q = range[p] + threadIdx.x; q < range[p + 1]; q += blockDim.x)
+        acc += partials[q];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0)
+        scal[p * S_COUNT + slot] = acc;
+}
+
+__global__ void k_after_setup(int nprob, const Fine *fines, double *scal)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob)
+        return;
+    double *s = scal + p * S_COUNT;
+    s[S_JBAR] = sqrt(s[S_JN2] / (double)fines[p].n);
+    s[S_JNORM] = sqrt(s[S_JN2]);
+}
+
+__global__ void k_rel(int nprob, double *scal, const int *active)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob || (active && !active[p]))
+        return;
+    double *s = scal + p * S_COUNT;
+    s[S_REL] = sqrt(s[S_RES2]) / s[S_JNORM];
+}
+
+__global__ void k_npcg_beta(int nprob, double *scal, const int *active, int first)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob || (active && !active[p]))
+        return;
+    double *s = scal + p * S_COUNT;
+    double beta = 0.0;
+    if (!first) {
+        beta = (s[S_GAMMA] - s[S_SIGMA]) / s[S_GAMMA_PREV];
+        if (!(beta > 0.0))
+            beta = 0.0;
+    }
+    s[S_BETA] = beta;
+    s[S_GAMMA_PREV] = s[S_GAMMA];
+}
+
+__global__ void k_npcg_theta(int nprob, double *scal, const int *active)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob || (active && !active[p]))
+        return;
+    double *s = scal + p * S_COUNT;
+    s[S_THETA] = s[S_RP] / s[S_PAP];
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid levels, precision T
+// ---------------------------------------------------------------------------
+
+__device__ inline long long fidx(const Grid &g, int i, int j, int k)
+{
+    return ((long long)i * (g.ny + 1) + j) * (g.nz + 1) + k;
+}
+
+// Face coefficient below cell (i,j,k) along axis ax (either side may be a
+// ghost; i,j,k may equal n along ax).
+template <typename T>
+__device__ inline T face_below(const Grid &g, int ax, int i, int j, int k)
+{
+    if (!g.fine) {
+        const long long nf = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+        return ((const T *)g.f)[ax * nf + fidx(g, i, j, k)];
+    }
+    const T *D = (const T *)g.D;
+    int li = i, lj = j, lk = k;
+    if (ax == 0) li -= 1; else if (ax == 1) lj -= 1; else lk -= 1;
+    const bool hi_in = i < g.nx && j < g.ny && k < g.nz;
+    const bool lo_in = li >= 0 && lj >= 0 && lk >= 0;
+    const long long sx = (long long)g.ny * g.nz;
+    if (hi_in && lo_in)
+        return (T)0.5 * (D[i * sx + (long long)j * g.nz + k] + D[li * sx + (long long)lj * g.nz + lk]);
+    const T Din = hi_in ? D[i * sx + (long long)j * g.nz + k] : D[li * sx + (long long)lj * g.nz + lk];
+    return (T)0.5 * (Din + (g.mirror ? Din : (T)g.dghost));
+}
+
+// num = b h^2 + sum_s F_s e_s, den = sa h^2 + sum_s F_s (ghost e = 0).
+template <typename T>
+__device__ inline void level_num_den(const Grid &g, const T *e, long long c, int i, int j, int k,
+                                     T &num, T &den)
+{
+    const T h2 = (T)g.h2;
+    const T *sa = (const T *)g.sa;
+    const T *b = (const T *)g.b;
+    const long long sx = (long long)g.ny * g.nz, sy = g.nz;
+    T n_ = b[c] * h2;
+    T d_ = sa[c] * h2;
+    T F;
+    F = face_below<T>(g, 0, i, j, k);
+    n_ = n_ + F * (i > 0 ? e[c - sx] : (T)0);
+    d_ = d_ + F;
+    F = face_below<T>(g, 0, i + 1, j, k);
+    n_ = n_ + F * (i < g.nx - 1 ? e[c + sx] : (T)0);
+    d_ = d_ + F;
+    F = face_below<T>(g, 1, i, j, k);
+    n_ = n_ + F * (j > 0 ? e[c - sy] : (T)0);
+    d_ = d_ + F;
+    F = face_below<T>(g, 1, i, j + 1, k);
+    n_ = n_ + F * (j < g.ny - 1 ? e[c + sy] : (T)0);
+    d_ = d_ + F;
+    F = face_below<T>(g, 2, i, j, k);
+    n_ = n_ + F * (k > 0 ? e[c - 1] : (T)0);
+    d_ = d_ + F;
+    F = face_below<T>(g, 2, i, j, k + 1);
+    n_ = n_ + F * (k < g.nz - 1 ? e[c + 1] : (T)0);
+    d_ = d_ + F;
+    num = n_;
+    den = d_;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_zero(const Grid *grids, const Task *tasks, int ntasks, const int *active)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &g = grids[tk.grid];
+        if (active && !active[g.prob])
+            continue;
+        T *e = (T *)g.e;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x)
+            e[tk.start + q] = (T)0;
+    }
+}
+
+// One red-black Gauss-Seidel half-sweep (in place: a colour reads only the
+// other colour): e_p <- w num/den + (1-w) e_p.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour, T omega)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &g = grids[tk.grid];
+        if (active && !active[g.prob])
+            continue;
+        T *e = (T *)g.e;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, g.ny, g.nz, i, j, k);
+            if (((i + j + k) & 1) != colour)
+                continue;
+            T num, den;
+            level_num_den<T>(g, e, c, i, j, k, num, den);
+            e[c] = omega * (num / den) + ((T)1 - omega) * e[c];
+        }
+    }
+}
+
+// Coarse right-hand side = 8-child mean of the fine residual b - A e.
+// Tasks run over the cells of the coarse grid.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &C = grids[tk.grid];
+        if (active && !active[C.prob])
+            continue;
+        const Grid &F = grids[C.finer];
+        const T *e = (const T *)F.e;
+        T *bc = (T *)C.b;
+        const T h2 = (T)F.h2;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long cc = tk.start + q;
+            int I, J, K;
+            decode(cc, C.ny, C.nz, I, J, K);
+            T s = (T)0;
+            for (int di = 0; di < 2; ++di)
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int dk = 0; dk < 2; ++dk) {
+                        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                        const long long c = ((long long)i * F.ny + j) * F.nz + k;
+                        T num, den;
+                        level_num_den<T>(F, e, c, i, j, k, num, den);
+                        s = s + (num - e[c] * den) / h2;
+                    }
+            bc[cc] = (T)0.125 * s;
+        }
+    }
+}
+
+// e_fine += e_coarse(parent).  Tasks run over the cells of the fine grid.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &F = grids[tk.grid];
+        if (active && !active[F.prob])
+            continue;
+        const Grid &C = grids[F.coarser];
+        T *ef = (T *)F.e;
+        const T *ec = (const T *)C.e;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, F.ny, F.nz, i, j, k);
+            ef[c] = ef[c] + ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
+        }
+    }
+}
+
+// Galerkin coarse faces: half the sum of the four fine faces on each coarse
+// face (in-face indices in lexicographic order).  Tasks run over the padded
+// (nx+1)(ny+1)(nz+1) face grid of the coarse level.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &C = grids[tk.grid];
+        if (active && !active[C.prob])
+            continue;
+        const Grid &F = grids[C.finer];
+        T *fc = (T *)C.f;
+        const long long nf = (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int I, J, K;
+            decode(c, C.ny + 1, C.nz + 1, I, J, K);
+            // x faces
+            T v = (T)0;
+            if (J < C.ny && K < C.nz) {
+                T s = (T)0;
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K + 1);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K + 1);
+                v = (T)0.5 * s;
+            }
+            fc[c] = v;
+            v = (T)0;
+            if (I < C.nx && K < C.nz) {
+                T s = (T)0;
+                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K);
+                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K + 1);
+                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K);
+                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K + 1);
+                v = (T)0.5 * s;
+            }
+            fc[nf + c] = v;
+            v = (T)0;
+            if (I < C.nx && J < C.ny) {
+                T s = (T)0;
+                s = s + face_below<T>(F, 2, 2 * I, 2 * J, 2 * K);
+                s = s + face_below<T>(F, 2, 2 * I, 2 * J + 1, 2 * K);
+                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J, 2 * K);
+                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J + 1, 2 * K);
+                v = (T)0.5 * s;
+            }
+            fc[2 * nf + c] = v;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_mean8_sa(const Grid *grids, const Task *tasks, int ntasks)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &C = grids[tk.grid];
+        const Grid &F = grids[C.finer];
+        const T *sf = (const T *)F.sa;
+        T *sc = (T *)C.sa;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long cc = tk.start + q;
+            int I, J, K;
+            decode(cc, C.ny, C.nz, I, J, K);
+            T s = (T)0;
+            for (int di = 0; di < 2; ++di)
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int dk = 0; dk < 2; ++dk)
+                        s = s + sf[((long long)(2 * I + di) * F.ny + (2 * J + dj)) * F.nz + (2 * K + dk)];
+            sc[cc] = (T)0.125 * s;
+        }
+    }
+}
+
+// Coarsest level: banded Cholesky of M = h^2 A (natural order, half
+// bandwidth bw = ny*nz), FP64.  Band entry (r, q), r - bw <= q <= r, sits at
+// band[r*(bw+1) + q - r + bw].
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_chol_factor(const Grid *grids, const int *ids, const int *active, int *fail)
+{
+    const Grid &g = grids[ids[blockIdx.x]];
+    if (active && !active[g.prob])
+        return;
+    const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
+    double *L = g.band;
+    const double h2 = g.h2;
+    const T *sa = (const T *)g.sa;
+    // assemble the lower band of M
+    for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x) {
+        const int r = (int)(x / W), d = (int)(x - (long long)r * W);
+        const int q = r - bw + d;
+        double v = 0.0;
+        int i, j, k;
+        decode(r, g.ny, g.nz, i, j, k);
+        if (q == r) {
+            v = (double)sa[r] * h2;
+            v = v + (double)face_below<T>(g, 0, i, j, k);
+            v = v + (double)face_below<T>(g, 0, i + 1, j, k);
+            v = v + (double)face_below<T>(g, 1, i, j, k);
+            v = v + (double)face_below<T>(g, 1, i, j + 1, k);
+            v = v + (double)face_below<T>(g, 2, i, j, k);
+            v = v + (double)face_below<T>(g, 2, i, j, k + 1);
+        } else if (q >= 0) {
+            const int off = r - q;
+            if (off == 1 && k > 0)
+                v = -(double)face_below<T>(g, 2, i, j, k);
+            else if (off == g.nz && j > 0)
+                v = -(double)face_below<T>(g, 1, i, j, k);
+            else if (off == bw && i > 0)
+                v = -(double)face_below<T>(g, 0, i, j, k);
+        }
+        L[x] = v;
+    }
+    __syncthreads();
+    __shared__ int bad;
+    if (threadIdx.x == 0)
+        bad = 0;
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        if (threadIdx.x == 0) {
+            double d = L[(long long)c * W + bw];
+            for (int q = (c - bw > 0 ? c - bw : 0); q < c; ++q) {
+                const double l = L[(long long)c * W + q - c + bw];
+                d = d - l * l;
+            }
+            if (!(d > 0.0))
+                bad = 1;
+            L[(long long)c * W + bw] = sqrt(d);
+        }
+        __syncthreads();
+        const double lcc = L[(long long)c * W + bw];
+        const int rmax = (c + bw < n - 1) ? c + bw : n - 1;
+        for (int r = c + 1 + threadIdx.x; r <= rmax; r += blockDim.x) {
+            double s = L[(long long)r * W + c - r + bw];
+            for (int q = (r - bw > 0 ? r - bw : 0); q < c; ++q)
+                s = s - L[(long long)r * W + q - r + bw] * L[(long long)c * W + q - c + bw];
+            L[(long long)r * W + c - r + bw] = s / lcc;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && bad)
+        fail[g.prob] = 1;
+}
+
+// Forward/backward substitution with the band factor; the inner products
+// are split over the first wave and reduced with shuffles.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_chol_solve(const Grid *grids, const int *ids, const int *active)
+{
+    extern __shared__ double y[];
+    const Grid &g = grids[ids[blockIdx.x]];
+    if (active && !active[g.prob])
+        return;
+    const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
+    const double *L = g.band;
+    const T *b = (const T *)g.b;
+    T *e = (T *)g.e;
+    const int lane = threadIdx.x;
+    for (int r = 0; r < n; ++r) {
+        double part = 0.0;
+        if (lane < kWave)
+            for (int q = (r - bw > 0 ? r - bw : 0) + lane; q < r; q += kWave)
+                part += L[(long long)r * W + q - r + bw] * y[q];
+        if (lane < kWave)
+            for (int o = kWave / 2; o > 0; o >>= 1)
+                part += __shfl_xor(part, o, kWave);
+        if (lane == 0)
+            y[r] = ((double)b[r] * g.h2 - part) / L[(long long)r * W + bw];
+        __syncthreads();
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double part = 0.0;
+        const int qmax = (r + bw < n - 1) ? r + bw : n - 1;
+        if (lane < kWave)
+            for (int q = r + 1 + lane; q <= qmax; q += kWave)
+                part += L[(long long)q * W + r - q + bw] * y[q];
+        if (lane < kWave)
+            for (int o = kWave / 2; o > 0; o >>= 1)
+                part += __shfl_xor(part, o, kWave);
+        if (lane == 0)
+            y[r] = (y[r] - part) / L[(long long)r * W + bw];
+        __syncthreads();
+    }
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+        e[r] = (T)y[r];
+}
+
+inline int grid_for(int ntasks)
+{
+    // Enough blocks to fill 256 CUs several times; blocks stride over tasks.
+    const int cap = 256 * 16;
+    return ntasks < cap ? (ntasks > 0 ? ntasks : 1) : cap;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
+                  const double *sigma_t, const double *albedo, const double *Q,
+                  double sigma_eps, double *partials, int mixed)
+{
+    hipLaunchKernelGGL(k_setup, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, f, tasks, ntasks,
+                       sigma_t, albedo, Q, sigma_eps, partials,
+                       mixed ? (float *)f.sa0 : (float *)nullptr);
+}
+
+void launch_sum_partials(hipStream_t s, int nprob, const int *range, const double *partials,
+                         double *scal, int slot, const int *active)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(nprob), dim3(kBlock), 0, s, range, partials, scal,
+                       slot, active);
+}
+
+void launch_after_setup(hipStream_t s, int nprob, const Fine *fines, double *scal)
+{
+    hipLaunchKernelGGL(k_after_setup, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, fines, scal);
+}
+
+void launch_init_phi(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                     const double *scal, int zero_dirs, int mixed)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_init_phi<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, scal, zero_dirs);
+    else
+        hipLaunchKernelGGL(k_init_phi<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, scal, zero_dirs);
+}
+
+void launch_limiter(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                    const int *active, const double *scal, int src, int dst, int use_dir,
+                    int dir_idx, int to_tmp, int mixed)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_limiter<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, scal, src, dst, use_dir, dir_idx, to_tmp);
+    else
+        hipLaunchKernelGGL(k_limiter<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, scal, src, dst, use_dir, dir_idx, to_tmp);
+}
+
+void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                     const int *active, int src, int use_tmp, int b0_idx, double *r_out,
+                     double *partials, int mixed)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_residual<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, src, use_tmp, b0_idx, r_out, partials);
+    else
+        hipLaunchKernelGGL(k_residual<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, src, use_tmp, b0_idx, r_out, partials);
+}
+
+void launch_rel(hipStream_t s, int nprob, double *scal, const int *active)
+{
+    hipLaunchKernelGGL(k_rel, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, active);
+}
+
+void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const int *active, int b0_idx, double *pg, double *ps, int mixed)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_npcg_dots<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, b0_idx, pg, ps);
+    else
+        hipLaunchKernelGGL(k_npcg_dots<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, b0_idx, pg, ps);
+}
+
+void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first)
+{
+    hipLaunchKernelGGL(k_npcg_beta, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, active,
+                       first);
+}
+
+void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                     const int *active, const double *scal, int b0_idx, int pin, int pout,
+                     double *prp, double *ppap, int mixed)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_npcg_dir<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, scal, b0_idx, pin, pout, prp, ppap);
+    else
+        hipLaunchKernelGGL(k_npcg_dir<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, scal, b0_idx, pin, pout, prp, ppap);
+}
+
+void launch_npcg_theta(hipStream_t s, int nprob, double *scal, const int *active)
+{
+    hipLaunchKernelGGL(k_npcg_theta, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, active);
+}
+
+void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const double *scal, int colour, double omega, double *partials)
+{
+    hipLaunchKernelGGL(k_alg1_pass, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines, tasks,
+                       ntasks, scal, colour, omega, partials);
+}
+
+template <typename T>
+void launch_zero(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                 const int *active)
+{
+    hipLaunchKernelGGL(k_zero<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks, ntasks,
+                       active);
+}
+
+template <typename T>
+void launch_smooth(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                   const int *active, int colour, double omega)
+{
+    hipLaunchKernelGGL(k_smooth<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
+                       ntasks, active, colour, (T)omega);
+}
+
+template <typename T>
+void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                     const int *active)
+{
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
+                       ntasks, active);
+}
+
+template <typename T>
+void launch_prolong(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                    const int *active)
+{
+    hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
+                       ntasks, active);
+}
+
+template <typename T>
+void launch_galerkin(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
+                     const int *active)
+{
+    hipLaunchKernelGGL(k_galerkin<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
+                       ntasks, active);
+}
+
+template <typename T>
+void launch_mean8_sa(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks)
+{
+    hipLaunchKernelGGL(k_mean8_sa<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
+                       ntasks);
+}
+
+template <typename T>
+void launch_chol_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
+                        const int *active, int *fail)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(k_chol_factor<T>, dim3(count), dim3(kBlock), 0, s, grids, ids, active,
+                           fail);
+}
+
+template <typename T>
+void launch_chol_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
+                       const int *active, int max_n)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(k_chol_solve<T>, dim3(count), dim3(kBlock), sizeof(double) * max_n, s,
+                           grids, ids, active);
+}
+
+#define FLD_INSTANTIATE(T)                                                                       \
+    template void launch_zero<T>(hipStream_t, const Grid *, const Task *, int, const int *);     \
+    template void launch_smooth<T>(hipStream_t, const Grid *, const Task *, int, const int *,    \
+                                   int, double);                                                 \
+    template void launch_restrict<T>(hipStream_t, const Grid *, const Task *, int, const int *); \
+    template void launch_prolong<T>(hipStream_t, const Grid *, const Task *, int, const int *);  \
+    template void launch_galerkin<T>(hipStream_t, const Grid *, const Task *, int, const int *); \
+    template void launch_mean8_sa<T>(hipStream_t, const Grid *, const Task *, int);              \
+    template void launch_chol_factor<T>(hipStream_t, const Grid *, const int *, int, const int *, \
+                                        int *);                                                  \
+    template void launch_chol_solve<T>(hipStream_t, const Grid *, const int *, int, const int *, \
+                                       int);
+
+FLD_INSTANTIATE(float)
+FLD_INSTANTIATE(double)
+
+}  // namespace fld

@@ -1,0 +1,71 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/fld.h, and rejects invalid arguments before touching a
+device."""
+import os
+import re
+
+import pytest
+
+import paper_1403_8105_amd as F
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "fld.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    decl = r"^(?:fld_status|void|const char)\s*\*?\s*(fld_[a-z_]+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 17
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert set(F.EXPORTS) <= set(syms)
+
+
+def test_default_options():
+    o = F.fld_default_options()
+    assert o.struct_size == F.C.sizeof(F.fld_options)
+    assert o.limiter == F.LIMITERS["lp"] and o.method == F.METHODS["mg"]
+    assert o.eps == 1e-20 and o.sigma_eps < 0 and o.tol == 1e-6
+    assert (o.nu1, o.nu2, o.max_coarsest) == (2, 2, 512)
+
+
+@pytest.mark.parametrize("kw,dims,h", [
+    ({}, (0, 4, 4), 0.1),
+    ({}, (8, 8, 8), 0.0),
+    ({}, (8, 8, 8), float("nan")),
+    ({"omega": 2.0}, (8, 8, 8), 0.1),
+    ({"omega_s": 0.0}, (8, 8, 8), 0.1),
+    ({"limiter": 9}, (8, 8, 8), 0.1),
+    ({"method": "rbsor", "precision": "mixed"}, (8, 8, 8), 0.1),
+    ({"tol": -1.0}, (8, 8, 8), 0.1),
+    ({"max_coarsest": 0}, (8, 8, 8), 0.1),
+    ({"nu1": 0, "nu2": 0}, (8, 8, 8), 0.1),
+    ({}, (100, 100, 100), 0.01),          # multigrid: coarsest 25^3 > 512
+    ({"limiter": "larsen", "larsen_n": 0.0}, (8, 8, 8), 0.1),
+])
+def test_create_rejects_invalid_arguments(kw, dims, h):
+    o = F.fld_default_options(**kw)
+    with pytest.raises(F.FldError) as ei:
+        F.fld_create(o, *dims, h)
+    assert ei.value.status == F.FLD_ERR_INVALID_ARGUMENT
+
+
+def test_struct_size_is_checked():
+    o = F.fld_default_options()
+    o.struct_size = 8
+    with pytest.raises(F.FldError):
+        F.fld_create(o, 8, 8, 8, 0.1)
+
+
+def test_null_handles():
+    lib = F.lib()
+    assert lib.fld_set_medium(None, None, None, None) == F.FLD_ERR_INVALID_ARGUMENT
+    assert lib.fld_solve(None, None, None, None) == F.FLD_ERR_INVALID_ARGUMENT
+    lib.fld_destroy(None)
+    lib.fld_batch_destroy(None)
+    assert F.fld_status_string(F.FLD_ERR_STATE) == "invalid call order"
