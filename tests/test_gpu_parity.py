@@ -158,7 +158,7 @@ def test_phi_init_and_zero_emission():
 def test_batch_equals_individual_solves():
     vols = media.batch_config(nvol=3, size_scale=0.25, seed=3)
     dims = [(v["n"],) * 3 for v in vols]
-    o = F.fld_default_options(precision="mixed", tol=1e-6, max_iters=400)
+    o = F.fld_default_options(precision="mixed", tol=1e-6, max_iters=3000)
     b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
     for i, v in enumerate(vols):
         F.fld_batch_set_volume(b, i, v["sigma_t"], v["albedo"], v["Q"])
@@ -170,7 +170,7 @@ def test_batch_equals_individual_solves():
     for v in vols:
         for c in range(3):
             s = gpu_solver((v["n"],) * 3, v["h"], v["sigma_t"], v["albedo"][c], v["Q"][c],
-                           precision="mixed", tol=1e-6, max_iters=400)
+                           precision="mixed", tol=1e-6, max_iters=3000)
             phi, r = s.solve()
             assert r["iterations"] == iters[q]
             np.testing.assert_array_equal(outs[q], phi)
