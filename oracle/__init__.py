@@ -36,7 +36,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("method", C.c_int), ("omega", C.c_double), ("omega_s", C.c_double),
                 ("nu1", C.c_int), ("nu2", C.c_int), ("max_coarsest", C.c_int),
                 ("max_iters", C.c_int), ("tol", C.c_double), ("check_every", C.c_int),
-                ("theta", C.c_double), ("step_mode", C.c_int)]
+                ("theta", C.c_double), ("step_mode", C.c_int), ("deflate_tau", C.c_double)]
 
 
 class Result(C.Structure):
@@ -77,6 +77,8 @@ def lib():
                                           C.c_int, _dp, _dp, _dp, _dp, _dp]
         L.fldo_coarse_apply.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_int, _dp, _dp, _dp, _dp]
+        L.fldo_clusters.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.c_double,
+                                    C.POINTER(C.c_int)]
         L.fldo_solve.argtypes = [P(Params), P(SolveOpts), _dp, _dp, _dp, _dp, _dp, _dp, C.c_int,
                                  P(Result)]
         _lib = L
@@ -236,12 +238,21 @@ def coarse_apply(D, sa, x1, h, d_ghost, mirror=False):
     return out
 
 
+def clusters(prob: Problem, tau: float = 1.0):
+    """Cluster labels (-1 outside clusters) and the number of clusters."""
+    nx, ny, nz = prob.shape
+    lab = np.empty(prob.shape, dtype=np.int32)
+    K = lib().fldo_clusters(nx, ny, nz, prob.params.h, _ptr(prob.sig_hat), float(tau),
+                            lab.ctypes.data_as(C.POINTER(C.c_int)))
+    return lab, K
+
+
 def solve_opts(method="mg", omega=1.0, omega_s=1.0, nu1=2, nu2=2, max_coarsest=512,
                max_iters=1000, tol=1e-6, check_every=1, theta=1.0,
-               step="optimal") -> SolveOpts:
+               step="optimal", deflate_tau=1.0) -> SolveOpts:
     return SolveOpts(METHODS[method], float(omega), float(omega_s), int(nu1), int(nu2),
                      int(max_coarsest), int(max_iters), float(tol), int(check_every),
-                     float(theta), {"fixed": 0, "optimal": 1}[step])
+                     float(theta), {"fixed": 0, "optimal": 1}[step], float(deflate_tau))
 
 
 def linear_vcycle(D, sa, b, h, d_ghost, mirror=False, **kw):

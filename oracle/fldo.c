@@ -676,6 +676,134 @@ static int hier_coarsen(mg_hier *H, int coarsen_sa, double d_ghost, int mirror)
     return fldo_cholesky_factor(Lc->nx * Lc->ny * Lc->nz, H->chol);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Cluster deflation (this project's addition to the multigrid              */
+/* preconditioner).  A cluster is a connected set of voxels joined by       */
+/* strong faces: faces whose classical-diffusion coefficient                */
+/* ((1/3)/sig_p + (1/3)/sig_s)/2 exceeds tau*L (L the grid extent).  Vacuum  */
+/* bubbles and the voxels around them form such clusters; the fluence is    */
+/* nearly constant over each and box coarsening cannot represent it.        */
+/* Clusters never touch each other, so the Galerkin matrix of their         */
+/* indicator functions is diagonal: d_c = sum_{p in c} sa_p + sum of the    */
+/* coefficients (/h^2) of faces leaving c.  One deflation step              */
+/* e1 = sum_c (sum_{p in c} r_p / d_c) 1_c precedes the V-cycle, which then */
+/* works on r - A e1.                                                       */
+/* ------------------------------------------------------------------------ */
+
+static int uf_find(int *parent, int x)
+{
+    while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+    }
+    return x;
+}
+
+static void uf_union(int *parent, int a, int b)
+{
+    a = uf_find(parent, a);
+    b = uf_find(parent, b);
+    if (a == b)
+        return;
+    if (a < b)
+        parent[b] = a;
+    else
+        parent[a] = b;
+}
+
+/* label[c] = cluster id (0..K-1, numbered by first voxel in index order) for
+ * voxels in clusters of two or more voxels, -1 otherwise.  Returns K. */
+int fldo_clusters(int nx, int ny, int nz, double h, const double *sig_hat, double tau, int *label)
+{
+    long n = (long)nx * ny * nz;
+    int nmax = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+    double thresh = tau * h * nmax;
+    int *parent = (int *)malloc(sizeof(int) * n);
+    int *size = (int *)calloc(n, sizeof(int));
+    for (long c = 0; c < n; ++c)
+        parent[c] = (int)c;
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+            for (int k = 0; k < nz; ++k) {
+                long c = idx3(ny, nz, i, j, k);
+                double dc = (1.0 / 3.0) / sig_hat[c];
+                long up[3] = {i + 1 < nx ? idx3(ny, nz, i + 1, j, k) : -1,
+                              j + 1 < ny ? idx3(ny, nz, i, j + 1, k) : -1,
+                              k + 1 < nz ? idx3(ny, nz, i, j, k + 1) : -1};
+                for (int a = 0; a < 3; ++a) {
+                    if (up[a] < 0)
+                        continue;
+                    double F = 0.5 * (dc + (1.0 / 3.0) / sig_hat[up[a]]);
+                    if (F > thresh)
+                        uf_union(parent, (int)c, (int)up[a]);
+                }
+            }
+    for (long c = 0; c < n; ++c)
+        size[uf_find(parent, (int)c)] += 1;
+    int K = 0;
+    int *id = (int *)malloc(sizeof(int) * n);
+    for (long c = 0; c < n; ++c)
+        id[c] = -1;
+    for (long c = 0; c < n; ++c) {
+        int root = uf_find(parent, (int)c);
+        if (size[root] < 2) {
+            label[c] = -1;
+            continue;
+        }
+        if (id[root] < 0)
+            id[root] = K++;
+        label[c] = id[root];
+    }
+    free(parent);
+    free(size);
+    free(id);
+    return K;
+}
+
+/* Diagonal of the cluster Galerkin matrix for the finest operator A(D). */
+static void cluster_diag(const mg_level *L, double d_ghost, int mirror, const int *label, int K,
+                         double *d)
+{
+    double h2 = L->h * L->h;
+    for (int q = 0; q < K; ++q)
+        d[q] = 0.0;
+    for (int i = 0; i < L->nx; ++i)
+        for (int j = 0; j < L->ny; ++j)
+            for (int k = 0; k < L->nz; ++k) {
+                long c = idx3(L->ny, L->nz, i, j, k);
+                int lc = label[c];
+                if (lc < 0)
+                    continue;
+                double v = L->sa[c];
+                for (int s = 0; s < 6; ++s) {
+                    int ax = NB[s][0] ? 0 : (NB[s][1] ? 1 : 2);
+                    int up = NB[s][0] + NB[s][1] + NB[s][2] > 0;
+                    int a = i + NB[s][0], b = j + NB[s][1], q = k + NB[s][2];
+                    int same = inside(L->nx, L->ny, L->nz, a, b, q) &&
+                               label[idx3(L->ny, L->nz, a, b, q)] == lc;
+                    if (same)
+                        continue;
+                    double F = up ? face(L, d_ghost, mirror, ax, a, b, q)
+                                  : face(L, d_ghost, mirror, ax, i, j, k);
+                    v = v + F / h2;
+                }
+                d[lc] = d[lc] + v;
+            }
+}
+
+/* e1 = sum_c (sum_{p in c} r_p / d_c) 1_c. */
+static void cluster_correction(long n, const int *label, int K, const double *d, const double *r,
+                               double *sum, double *e1)
+{
+    for (int q = 0; q < K; ++q)
+        sum[q] = 0.0;
+    for (long c = 0; c < n; ++c)
+        if (label[c] >= 0)
+            sum[label[c]] = sum[label[c]] + r[c];
+    for (long c = 0; c < n; ++c)
+        e1[c] = label[c] >= 0 ? sum[label[c]] / d[label[c]] : 0.0;
+}
+
 /* Linear V-cycle on a caller-given finest system (test hook): e0 receives
  * one V(nu1,nu2) cycle from zero for A(D0) e = b0. */
 int fldo_linear_vcycle(int nx, int ny, int nz, double h, double d_ghost, int mirror,
@@ -787,7 +915,8 @@ static int solve_alg1(const fldo_params *p, const fldo_solve_opts *o, const doub
  * Outer iteration k:
  *   D^k = limiter pass on phi^k (every voxel), r^k = j - A(D^k) phi^k (FP64),
  *   stop when ||r^k||/||j|| <= tol;
- *   e^k = one V-cycle for A(D^k) e = r^k (the preconditioner);
+ *   e^k = the preconditioner applied to r^k: cluster deflation e1, then one
+ *   V-cycle for A(D^k) e = r^k - A(D^k) e1, e^k = e1 + e;
  *   gamma_k = r^k.e^k; beta_k = max(0, (gamma_k - e^k.r^{k-1}) / gamma_{k-1})
  *   (Polak-Ribiere, restarted when negative; beta_0 = 0);
  *   p^k = e^k + beta_k p^{k-1};
@@ -814,7 +943,15 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
     double *dir = (double *)calloc(n, sizeof(double));
     double *q = (double *)malloc(sizeof(double) * n);
     double *r_prev = (double *)calloc(n, sizeof(double));
-    double *r = H.lv[0].b, *e = H.lv[0].e;
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *e1 = (double *)calloc(n, sizeof(double));
+    double *e = H.lv[0].e;
+    int *label = (int *)malloc(sizeof(int) * n);
+    int K = o->deflate_tau > 0.0
+                ? fldo_clusters(p->nx, p->ny, p->nz, p->h, sig_hat, o->deflate_tau, label)
+                : 0;
+    double *dcl = (double *)malloc(sizeof(double) * (K > 0 ? K : 1));
+    double *scl = (double *)malloc(sizeof(double) * (K > 0 ? K : 1));
     H.lv[0].D = D;
     memcpy(H.lv[0].sa, sig_a, sizeof(double) * n);
     int it = 0, len = 0, status = FLDO_NOT_CONVERGED, first = 1;
@@ -828,7 +965,20 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
         if (it >= o->max_iters) { status = FLDO_NOT_CONVERGED; break; }
         if (hier_coarsen(&H, first, d_ghost, p->mirror_d)) { status = FLDO_DIVERGED; break; }
         first = 0;
+        /* preconditioner: cluster deflation, then one V-cycle on the rest */
+        if (K > 0) {
+            cluster_diag(&H.lv[0], d_ghost, p->mirror_d, label, K, dcl);
+            cluster_correction(n, label, K, dcl, r, scl, e1);
+            level_apply(&H.lv[0], d_ghost, p->mirror_d, e1, q);
+            for (long c = 0; c < n; ++c)
+                H.lv[0].b[c] = r[c] - q[c];
+        } else {
+            memcpy(H.lv[0].b, r, sizeof(double) * n);
+        }
         vcycle(H.lv, 0, nlev, o, d_ghost, p->mirror_d, H.chol);
+        if (K > 0)
+            for (long c = 0; c < n; ++c)
+                e[c] = e1[c] + e[c];
         double theta;
         if (o->step_mode == 1) {
             double gamma = 0.0, e_rprev = 0.0;
@@ -865,6 +1015,11 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
     free(dir);
     free(q);
     free(r_prev);
+    free(r);
+    free(e1);
+    free(label);
+    free(dcl);
+    free(scl);
     hier_free(&H);
     res->status = status;
     res->iterations = it;

@@ -51,6 +51,7 @@ typedef struct fldo_solve_opts {
     int check_every;          /* Alg. 1: iterations between residual checks */
     double theta;             /* multigrid correction step (step_mode 0) */
     int step_mode;            /* 0: p = e, fixed theta; 1: nonlinear PCG direction and step */
+    double deflate_tau;       /* cluster threshold (x grid extent); <= 0 disables deflation */
 } fldo_solve_opts;
 
 typedef struct fldo_result {
@@ -86,6 +87,7 @@ void fldo_level_residual(int nx, int ny, int nz, double h, double d_ghost, int m
                          double *r);
 int fldo_coarse_apply(int nx, int ny, int nz, double h, double d_ghost, int mirror,
                       const double *D0, const double *sa0, const double *x1, double *out1);
+int fldo_clusters(int nx, int ny, int nz, double h, const double *sig_hat, double tau, int *label);
 int fldo_solve(const fldo_params *p, const fldo_solve_opts *o, const double *sig_hat,
                const double *sig_a, const double *j_src, double *phi, double *D, double *hist,
                int cap, fldo_result *res);

@@ -193,3 +193,51 @@ def test_single_level_vcycle_is_exact(oracle_mod):
     M = assemble(D, sa, h, EPS * h).tocsc()
     ref = spl.spsolve(M, b.ravel() * h * h).reshape(b.shape)
     np.testing.assert_allclose(e, ref, rtol=1e-11, atol=1e-12 * np.abs(ref).max())
+
+
+def test_clusters_match_connected_components(oracle_mod):
+    # Clusters = connected components of the graph of strong faces (classical
+    # coefficient ((1/3)/sig_p + (1/3)/sig_s)/2 > tau * L), computed here with scipy.
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    st, al, Q, h = media.config("cloud256", n=24)
+    prob = oracle_mod.setup(st, al, Q, h)
+    for tau in (0.3, 1.0, 5.0):
+        lab, K = oracle_mod.clusters(prob, tau)
+        n = st.size
+        idx = np.arange(n).reshape(st.shape)
+        Dc = (1.0 / 3.0) / prob.sig_hat
+        rows, cols = [], []
+        for ax in range(3):
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[ax], hi[ax] = slice(0, -1), slice(1, None)
+            F = 0.5 * (Dc[tuple(lo)] + Dc[tuple(hi)])
+            m = F > tau * h * 24
+            rows.append(idx[tuple(lo)][m])
+            cols.append(idx[tuple(hi)][m])
+        r, c = np.concatenate(rows), np.concatenate(cols)
+        G = sp.coo_matrix((np.ones(len(r)), (r, c)), shape=(n, n))
+        nc, comp = connected_components(G, directed=False)
+        sizes = np.bincount(comp)
+        in_cluster = sizes[comp] > 1
+        assert K == int((sizes > 1).sum())
+        np.testing.assert_array_equal(lab.ravel() >= 0, in_cluster)
+        # same partition: equal labels <=> equal components
+        a, b = lab.ravel()[in_cluster], comp[in_cluster]
+        pairs = set(zip(a.tolist(), b.tolist()))
+        assert len(pairs) == K == len(set(a.tolist())) == len(set(b.tolist()))
+        # numbering: by first voxel in index order
+        first = [int(np.argmax(lab.ravel() == q)) for q in range(K)]
+        assert first == sorted(first)
+
+
+def test_deflation_keeps_the_fixed_point(oracle_mod):
+    st, al, Q, h = media.config("cloud256", n=32)
+    prob = oracle_mod.setup(st, al, Q, h)
+    a = oracle_mod.solve(prob, method="mg", tol=1e-11, max_iters=3000, deflate_tau=0.0)
+    b = oracle_mod.solve(prob, method="mg", tol=1e-11, max_iters=3000, deflate_tau=1.0)
+    assert a.status == b.status == "converged"
+    assert b.iterations < a.iterations / 2          # the point of deflating
+    assert np.linalg.norm(a.phi - b.phi) <= 1e-9 * np.linalg.norm(a.phi)
