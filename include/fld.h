@@ -95,6 +95,11 @@ typedef struct fld_options {
     int device;           /* HIP device ordinal (default 0)                              */
     void *stream;         /* hipStream_t for all work; NULL = the context's own stream   */
     int timing;           /* 1: bracket the hot kernels with HIP events (fld_report.kernel_*) */
+    double deflate_tau;   /* multigrid: cluster-deflation threshold in units of the grid
+                             extent L; voxels joined by faces whose classical coefficient
+                             ((1/3)/sig_p + (1/3)/sig_s)/2 exceeds tau*L form clusters whose
+                             constant mode is removed before each V-cycle; <= 0 disables
+                             (default 1)                                                  */
 } fld_options;
 
 typedef struct fld_report {

@@ -73,6 +73,15 @@ struct fld_engine_impl {
 
     Fine *d_fines = nullptr;
     Grid *d_grids[2] = {nullptr, nullptr};
+    Grid *d_grids_defl = nullptr;   // level-0 right-hand side = deflated b1
+    // cluster deflation (built when the media are set)
+    bool defl_enabled = false, use_defl = false;
+    int ncl_total = 0;
+    CTask *d_ctasks = nullptr;
+    int n_ctasks = 0;
+    int *d_crange = nullptr, *d_cprob = nullptr;
+    double *d_alpha = nullptr, *d_cpd = nullptr, *d_cps = nullptr;
+    std::vector<void *> defl_allocs;
     int ngrids = 0;
     DevList fine_tasks;
     std::vector<int> fine_range;   // host copy, nprob+1
@@ -148,6 +157,8 @@ struct fld_engine_impl {
         for (hipEvent_t e : ev_pool)
             hipEventDestroy(e);
         for (void *p : allocs)
+            hipFree(p);
+        for (void *p : defl_allocs)
             hipFree(p);
         if (own_stream && stream)
             hipStreamDestroy(stream);
@@ -273,6 +284,8 @@ struct fld_engine_impl {
                 CK(dalloc(&f.e0, NT));
                 CK(dalloc(&f.p[0], NT));
                 CK(dalloc(&f.p[1], NT));
+                if (opt.deflate_tau > 0.0)
+                    CK(dalloc(&f.b1, NT));
                 if (mixed) {
                     CK(dalloc(&f.D0, NT));
                     CK(dalloc(&f.sa0, NT));
@@ -372,6 +385,15 @@ struct fld_engine_impl {
             HK(hipMemcpy(d_grids[q], grids[q].data(), sizeof(Grid) * ngrids, hipMemcpyHostToDevice),
                "hipMemcpy grids");
         }
+        defl_enabled = opt.deflate_tau > 0.0;
+        if (defl_enabled) {
+            std::vector<Grid> gd = grids[0];
+            for (int p = 0; p < nprob; ++p)
+                gd[probs[p].gid0].b = probs[p].fine.b1;
+            CK(dalloc(&d_grids_defl, sizeof(Grid) * ngrids));
+            HK(hipMemcpy(d_grids_defl, gd.data(), sizeof(Grid) * ngrids, hipMemcpyHostToDevice),
+               "hipMemcpy grids");
+        }
         for (int l = 0; l < max_levels; ++l) {
             std::vector<Task> m, r, g;
             std::vector<int> ch;
@@ -418,8 +440,147 @@ struct fld_engine_impl {
         return FLD_OK;
     }
 
+    // Clusters of voxels joined by strong faces (classical coefficient
+    // ((1/3)/sig_p + (1/3)/sig_s)/2 > tau*L), labelled by union-find and
+    // numbered by their first voxel in index order; only clusters of two or
+    // more voxels are kept.
+    static int label_clusters(const Vol &V, const std::vector<double> &sh, double tau,
+                              std::vector<int> &label)
+    {
+        const long long n = V.n;
+        const double thresh = tau * V.h * std::max(V.nx, std::max(V.ny, V.nz));
+        std::vector<int> parent(n), size(n, 0), id(n, -1);
+        for (long long c = 0; c < n; ++c)
+            parent[c] = (int)c;
+        auto find = [&](int x) {
+            while (parent[x] != x) {
+                parent[x] = parent[parent[x]];
+                x = parent[x];
+            }
+            return x;
+        };
+        auto unite = [&](int a, int b) {
+            a = find(a);
+            b = find(b);
+            if (a != b)
+                parent[std::max(a, b)] = std::min(a, b);
+        };
+        const long long sx = (long long)V.ny * V.nz, sy = V.nz;
+        for (int i = 0; i < V.nx; ++i)
+            for (int j = 0; j < V.ny; ++j)
+                for (int k = 0; k < V.nz; ++k) {
+                    const long long c = i * sx + j * sy + k;
+                    const double dc = (1.0 / 3.0) / sh[c];
+                    if (i + 1 < V.nx && 0.5 * (dc + (1.0 / 3.0) / sh[c + sx]) > thresh)
+                        unite((int)c, (int)(c + sx));
+                    if (j + 1 < V.ny && 0.5 * (dc + (1.0 / 3.0) / sh[c + sy]) > thresh)
+                        unite((int)c, (int)(c + sy));
+                    if (k + 1 < V.nz && 0.5 * (dc + (1.0 / 3.0) / sh[c + 1]) > thresh)
+                        unite((int)c, (int)(c + 1));
+                }
+        for (long long c = 0; c < n; ++c)
+            size[find((int)c)] += 1;
+        int K = 0;
+        label.assign(n, -1);
+        for (long long c = 0; c < n; ++c) {
+            const int r = find((int)c);
+            if (size[r] < 2)
+                continue;
+            if (id[r] < 0)
+                id[r] = K++;
+            label[c] = id[r];
+        }
+        return K;
+    }
+
+    fld_status build_clusters()
+    {
+        for (void *q : defl_allocs)
+            hipFree(q);
+        defl_allocs.clear();
+        use_defl = false;
+        ncl_total = 0;
+        n_ctasks = 0;
+        if (!mg || !defl_enabled)
+            return FLD_OK;
+        auto dal = [&](void **q, size_t bytes) -> fld_status {
+            hipError_t er = hipMalloc(q, bytes ? bytes : 8);
+            if (er != hipSuccess)
+                return hip_fail(er, "hipMalloc clusters");
+            defl_allocs.push_back(*q);
+            return FLD_OK;
+        };
+        std::vector<int> vK(vols.size());
+        std::vector<int *> vlabel(vols.size()), vcells(vols.size());
+        std::vector<std::vector<int>> vstart(vols.size());
+        for (size_t v = 0; v < vols.size(); ++v) {
+            const Vol &V = vols[v];
+            std::vector<double> sh(V.n);
+            HK(hipMemcpy(sh.data(), V.sig_hat, 8 * V.n, hipMemcpyDeviceToHost), "sig_hat D2H");
+            std::vector<int> label;
+            const int K = label_clusters(V, sh, opt.deflate_tau, label);
+            vK[v] = K;
+            // voxels of every cluster, cluster by cluster, index order inside
+            std::vector<int> start(K + 1, 0), cells;
+            for (long long c = 0; c < V.n; ++c)
+                if (label[c] >= 0)
+                    ++start[label[c] + 1];
+            for (int q = 0; q < K; ++q)
+                start[q + 1] += start[q];
+            cells.resize(start[K]);
+            std::vector<int> fill(start.begin(), start.end() - 1);
+            for (long long c = 0; c < V.n; ++c)
+                if (label[c] >= 0)
+                    cells[fill[label[c]]++] = (int)c;
+            CK(dal((void **)&vlabel[v], sizeof(int) * V.n));
+            CK(dal((void **)&vcells[v], sizeof(int) * cells.size()));
+            HK(hipMemcpy(vlabel[v], label.data(), sizeof(int) * V.n, hipMemcpyHostToDevice), "labels");
+            if (!cells.empty())
+                HK(hipMemcpy(vcells[v], cells.data(), sizeof(int) * cells.size(),
+                             hipMemcpyHostToDevice), "cluster cells");
+            vstart[v] = start;
+        }
+        std::vector<CTask> ct;
+        std::vector<int> crange(1, 0), cprob;
+        std::vector<Fine> hf(nprob);
+        for (int p = 0; p < nprob; ++p) {
+            Fine &f = probs[p].fine;
+            const int v = probs[p].vol;
+            f.label = vlabel[v];
+            f.ccells = vcells[v];
+            f.cbase = ncl_total;
+            f.ncl = vK[v];
+            for (int q = 0; q < vK[v]; ++q) {
+                for (int s0 = vstart[v][q]; s0 < vstart[v][q + 1]; s0 += kTaskCells)
+                    ct.push_back(CTask{p, ncl_total + q, s0,
+                                       std::min(kTaskCells, vstart[v][q + 1] - s0)});
+                crange.push_back((int)ct.size());
+                cprob.push_back(p);
+            }
+            ncl_total += vK[v];
+            hf[p] = f;
+        }
+        HK(hipMemcpy(d_fines, hf.data(), sizeof(Fine) * nprob, hipMemcpyHostToDevice), "fines");
+        if (ncl_total == 0)
+            return FLD_OK;
+        n_ctasks = (int)ct.size();
+        CK(dal((void **)&d_ctasks, sizeof(CTask) * ct.size()));
+        CK(dal((void **)&d_crange, sizeof(int) * crange.size()));
+        CK(dal((void **)&d_cprob, sizeof(int) * cprob.size()));
+        CK(dal((void **)&d_alpha, sizeof(double) * ncl_total));
+        CK(dal((void **)&d_cpd, sizeof(double) * ct.size()));
+        CK(dal((void **)&d_cps, sizeof(double) * ct.size()));
+        HK(hipMemcpy(d_ctasks, ct.data(), sizeof(CTask) * ct.size(), hipMemcpyHostToDevice), "ctasks");
+        HK(hipMemcpy(d_crange, crange.data(), sizeof(int) * crange.size(), hipMemcpyHostToDevice), "crange");
+        HK(hipMemcpy(d_cprob, cprob.data(), sizeof(int) * cprob.size(), hipMemcpyHostToDevice), "cprob");
+        use_defl = true;
+        return FLD_OK;
+    }
+
     fld_status finish_medium()
     {
+        HK(hipStreamSynchronize(stream), "medium sync");
+        CK(build_clusters());
         if (mg) {
             for (int l = 0; l + 1 < max_levels; ++l) {
                 if (!rest[l].n)
@@ -495,10 +656,11 @@ struct fld_engine_impl {
         return c;
     }
 
+    // par: parity of the level-0 right-hand side buffer, -1: the deflated one
     template <typename T>
     void vcycle(int par)
     {
-        Grid *G = d_grids[par];
+        Grid *G = par < 0 ? d_grids_defl : d_grids[par];
         for (int l = 0; l < max_levels; ++l) {
             if (mid[l].n) {
                 launch_zero<T>(stream, G, mid[l].d, mid[l].n, d_active);
@@ -620,19 +782,27 @@ struct fld_engine_impl {
             if (!n_active)
                 break;
             CK(sync_active());
+            if (use_defl) {
+                launch_defl_reduce(stream, d_fines, d_ctasks, n_ctasks, d_active, k & 1, d_cpd, d_cps,
+                                   mixed);
+                launch_defl_finish(stream, ncl_total, d_crange, d_cprob, d_cpd, d_cps, d_alpha,
+                                   d_active);
+                launch_defl_apply(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_alpha,
+                                  mixed);
+            }
             if (mixed) {
                 coarsen_and_factor<float>();
-                vcycle<float>(k & 1);
+                vcycle<float>(use_defl ? -1 : (k & 1));
             } else {
                 coarsen_and_factor<double>();
-                vcycle<double>(k & 1);
+                vcycle<double>(use_defl ? -1 : (k & 1));
             }
             for (int p = 0; p < N; ++p)
                 if (h_active[p])
                     for (int l = 0; l + 1 < probs[p].nlev; ++l)
                         *updates += (double)probs[p].lv[l].n * (opt.nu1 + opt.nu2);
             launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1,
-                             d_part[0], d_part[1], mixed);
+                             d_part[0], d_part[1], use_defl ? d_alpha : nullptr, mixed);
             launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
             launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
             launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0);
@@ -771,6 +941,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (!(o->tol >= 0.0 && std::isfinite(o->tol))) { err = "tol must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->check_every < 1) { err = "check_every must be >= 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->device < 0) { err = "device must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!std::isfinite(o->deflate_tau)) { err = "deflate_tau must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -852,6 +1023,7 @@ fld_status fld_default_options(fld_options *o)
     o->device = 0;
     o->stream = nullptr;
     o->timing = 0;
+    o->deflate_tau = 1.0;
     return FLD_OK;
 }
 

@@ -50,6 +50,20 @@ struct Fine {
     void *e0;            // finest correction (precision T)
     void *p[2];          // search-direction ping-pong (precision T)
     void *D0, *sa0;      // finest coefficients in precision T
+    const int *label;    // cluster of each voxel (-1: none), per volume
+    const int *ccells;   // voxels of every cluster, cluster by cluster
+    int cbase;           // first global cluster index of this problem
+    int ncl;             // clusters of this problem
+    void *b1;            // deflated V-cycle right-hand side (precision T)
+};
+
+// A run of cluster voxels: entries [start, start+count) of the problem's
+// ccells list, all in global cluster `cl`.
+struct CTask {
+    int prob;
+    int cl;
+    int start;
+    int count;
 };
 
 // Per-problem device scalars.
@@ -83,12 +97,22 @@ void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      double *partials, int mixed);
 void launch_rel(hipStream_t s, int nprob, double *scal, const int *active);
 void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
-                      const int *active, int b0_idx, double *pg, double *ps, int mixed);
+                      const int *active, int b0_idx, double *pg, double *ps,
+                      const double *alpha, int mixed);
 void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first);
 void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                      const int *active, const double *scal, int b0_idx, int pin, int pout,
                      double *prp, double *ppap, int mixed);
 void launch_npcg_theta(hipStream_t s, int nprob, double *scal, const int *active);
+// Cluster deflation: per-task partial sums of the cluster Galerkin diagonal
+// and of the right-hand side, the per-cluster coefficients alpha = s/d, the
+// deflated right-hand side b1 = b0 - A e1, and e0 += e1.
+void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
+                        const int *active, int b0_idx, double *pd, double *ps, int mixed);
+void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *cprob,
+                        const double *pd, const double *ps, double *alpha, const int *active);
+void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                       const int *active, int b0_idx, const double *alpha, int mixed);
 void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const double *scal, int colour, double omega, double *partials);
 

@@ -254,10 +254,11 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
 }
 
 // gamma = b0 . e and sigma = e . b0_prev (conjugate-gradient coefficients).
+// With deflation the cluster correction is first added: e0 += alpha[label].
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
-            double *pg, double *ps)
+            double *pg, double *ps, const double *alpha)
 {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
@@ -266,11 +267,19 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
             continue;
         const T *b = (const T *)f.b0[b0_idx];
         const T *bp = (const T *)f.b0[b0_idx ^ 1];
-        const T *e = (const T *)f.e0;
+        T *e = (T *)f.e0;
         double g = 0.0, sg = 0.0;
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
-            const double ev = (double)e[c];
+            double ev = (double)e[c];
+            if (alpha) {
+                const int l = f.label[c];
+                if (l >= 0) {
+                    ev = alpha[f.cbase + l] + ev;
+                    e[c] = (T)ev;
+                    ev = (double)e[c];
+                }
+            }
             g += (double)b[c] * ev;
             sg += ev * (double)bp[c];
         }
@@ -343,6 +352,151 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
         if (threadIdx.x == 0) {
             prp[t] = arp;
             ppap[t] = apap;
+        }
+    }
+}
+
+// Cluster deflation, reduction pass: for the voxels of each task (all in one
+// cluster) the contributions to the cluster Galerkin diagonal
+// d_c = sum sa + sum_{faces leaving c} F/h^2 and to s_c = sum b0.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, int b0_idx,
+              double *pd, double *ps)
+{
+    for (int t = blockIdx.x; t < nct; t += gridDim.x) {
+        const CTask tk = ct[t];
+        const Fine &f = fines[tk.prob];
+        if (active && !active[f.prob]) {
+            if (threadIdx.x == 0) {
+                pd[t] = 0.0;
+                ps[t] = 0.0;
+            }
+            continue;
+        }
+        const T *D = (const T *)f.D0;
+        const T *sa = (const T *)f.sa0;
+        const T *b = (const T *)f.b0[b0_idx];
+        const int *lab = f.label;
+        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
+        const double gD0 = (double)(T)f.dghost;
+        double ad = 0.0, as = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = f.ccells[tk.start + q];
+            int i, j, k;
+            decode(c, f.ny, f.nz, i, j, k);
+            const int lc = lab[c];
+            const double Dc = (double)D[c];
+            const double gD = f.mirror ? Dc : gD0;
+            double v = (double)sa[c];
+            auto cut = [&](bool in, long long x) {
+                if (in && lab[x] == lc)
+                    return;
+                const double F = 0.5 * (Dc + (in ? (double)D[x] : gD));
+                v = v + F / f.h2;
+            };
+            cut(i > 0, c - sx);
+            cut(i < f.nx - 1, c + sx);
+            cut(j > 0, c - sy);
+            cut(j < f.ny - 1, c + sy);
+            cut(k > 0, c - 1);
+            cut(k < f.nz - 1, c + 1);
+            ad += v;
+            as += (double)b[c];
+        }
+        ad = block_sum(ad);
+        as = block_sum(as);
+        if (threadIdx.x == 0) {
+            pd[t] = ad;
+            ps[t] = as;
+        }
+    }
+}
+
+// alpha_c = s_c / d_c, one block per cluster (sums of its task partials).
+__global__ void __launch_bounds__(kBlock)
+k_defl_finish(const int *crange, const int *cprob, const double *pd, const double *ps,
+              double *alpha, const int *active)
+{
+    const int c = blockIdx.x;
+    if (active && !active[cprob[c]])
+        return;
+    double d = 0.0, s = 0.0;
+    for (int q = crange[c] + threadIdx.x; q < crange[c + 1]; q += blockDim.x) {
+        d += pd[q];
+        s += ps[q];
+    }
+    d = block_sum(d);
+    s = block_sum(s);
+    if (threadIdx.x == 0)
+        alpha[c] = s / d;
+}
+
+// Deflated right-hand side b1 = b0 - A e1 with e1 = alpha[label] (zero
+// outside clusters); A is the finest operator in the coefficients of the
+// V-cycle, (A x)_c = (x_c den - sum_s F_s x_s)/h^2.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
+             const double *alpha)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        if (active && !active[f.prob])
+            continue;
+        const T *D = (const T *)f.D0;
+        const T *sa = (const T *)f.sa0;
+        const T *b = (const T *)f.b0[b0_idx];
+        T *b1 = (T *)f.b1;
+        const int *lab = f.label;
+        const double *al = alpha + f.cbase;
+        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
+        const double gD0 = (double)(T)f.dghost;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            int i, j, k;
+            decode(c, f.ny, f.nz, i, j, k);
+            auto ev = [&](bool in, long long x) {
+                if (!in)
+                    return 0.0;
+                const int l = lab[x];
+                return l >= 0 ? al[l] : 0.0;
+            };
+            const double e_c = ev(true, c);
+            const double exm = ev(i > 0, c - sx), exp_ = ev(i < f.nx - 1, c + sx);
+            const double eym = ev(j > 0, c - sy), eyp = ev(j < f.ny - 1, c + sy);
+            const double ezm = ev(k > 0, c - 1), ezp = ev(k < f.nz - 1, c + 1);
+            if (e_c == 0.0 && exm == 0.0 && exp_ == 0.0 && eym == 0.0 && eyp == 0.0 &&
+                ezm == 0.0 && ezp == 0.0) {
+                b1[c] = b[c];
+                continue;
+            }
+            const double Dc = (double)D[c];
+            const double gD = f.mirror ? Dc : gD0;
+            double nb = 0.0;
+            double den = (double)sa[c] * f.h2;
+            double F;
+            F = 0.5 * (Dc + (i > 0 ? (double)D[c - sx] : gD));
+            nb = nb + F * exm;
+            den = den + F;
+            F = 0.5 * (Dc + (i < f.nx - 1 ? (double)D[c + sx] : gD));
+            nb = nb + F * exp_;
+            den = den + F;
+            F = 0.5 * (Dc + (j > 0 ? (double)D[c - sy] : gD));
+            nb = nb + F * eym;
+            den = den + F;
+            F = 0.5 * (Dc + (j < f.ny - 1 ? (double)D[c + sy] : gD));
+            nb = nb + F * eyp;
+            den = den + F;
+            F = 0.5 * (Dc + (k > 0 ? (double)D[c - 1] : gD));
+            nb = nb + F * ezm;
+            den = den + F;
+            F = 0.5 * (Dc + (k < f.nz - 1 ? (double)D[c + 1] : gD));
+            nb = nb + F * ezp;
+            den = den + F;
+            const double Ae = (e_c * den - nb) / f.h2;
+            b1[c] = (T)((double)b[c] - Ae);
         }
     }
 }
@@ -901,14 +1055,47 @@ void launch_rel(hipStream_t s, int nprob, double *scal, const int *active)
 }
 
 void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
-                      const int *active, int b0_idx, double *pg, double *ps, int mixed)
+                      const int *active, int b0_idx, double *pg, double *ps,
+                      const double *alpha, int mixed)
 {
     if (mixed)
         hipLaunchKernelGGL(k_npcg_dots<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, b0_idx, pg, ps);
+                           tasks, ntasks, active, b0_idx, pg, ps, alpha);
     else
         hipLaunchKernelGGL(k_npcg_dots<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, b0_idx, pg, ps);
+                           tasks, ntasks, active, b0_idx, pg, ps, alpha);
+}
+
+void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
+                        const int *active, int b0_idx, double *pd, double *ps, int mixed)
+{
+    if (nct <= 0)
+        return;
+    if (mixed)
+        hipLaunchKernelGGL(k_defl_reduce<float>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
+                           ct, nct, active, b0_idx, pd, ps);
+    else
+        hipLaunchKernelGGL(k_defl_reduce<double>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
+                           ct, nct, active, b0_idx, pd, ps);
+}
+
+void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *cprob,
+                        const double *pd, const double *ps, double *alpha, const int *active)
+{
+    if (ncl_total > 0)
+        hipLaunchKernelGGL(k_defl_finish, dim3(ncl_total), dim3(kBlock), 0, s, crange, cprob, pd,
+                           ps, alpha, active);
+}
+
+void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                       const int *active, int b0_idx, const double *alpha, int mixed)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_defl_apply<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, b0_idx, alpha);
+    else
+        hipLaunchKernelGGL(k_defl_apply<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, b0_idx, alpha);
 }
 
 void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first)

@@ -201,3 +201,30 @@ def test_not_converged_still_writes_phi():
     phi, rep = s.solve()
     assert rep["status"] == F.FLD_ERR_NOT_CONVERGED and rep["iterations"] == 2
     assert np.all(np.isfinite(phi)) and phi.max() > 0
+
+
+@pytest.mark.parametrize("tau", [0.0, 1.0])
+def test_mg_deflation_iterate_parity(tau):
+    # the 256^3-generator medium has strongly coupled vacuum clusters
+    st, al, Q, h = media.config("cloud256", n=32)
+    prob = oracle.setup(st, al, Q, h)
+    lab, K = oracle.clusters(prob, 1.0)
+    assert K > 0
+    for k in (1, 2, 6, 15):
+        ref = oracle.solve(prob, method="mg", tol=0.0, max_iters=k, deflate_tau=tau)
+        s = gpu_solver(st.shape, h, st, al, Q, tol=0.0, max_iters=k, deflate_tau=tau)
+        phi, rep = s.solve()
+        np.testing.assert_allclose(rep["history"], ref.history, rtol=1e-9)
+        assert rel_l2(phi, ref.phi) <= 1e-10, k
+
+
+def test_mg_deflated_solve_converges_like_the_oracle():
+    st, al, Q, h = media.config("cloud256", n=32)
+    prob = oracle.setup(st, al, Q, h)
+    ref = oracle.solve(prob, method="mg", tol=1e-8, max_iters=3000)
+    for prec in ("fp64", "mixed"):
+        s = gpu_solver(st.shape, h, st, al, Q, precision=prec, tol=1e-8, max_iters=3000)
+        phi, rep = s.solve()
+        assert rep["status"] == F.FLD_OK
+        assert rep["iterations"] <= 1.25 * ref.iterations
+        assert rel_l2(phi, ref.phi) <= (1e-6 if prec == "mixed" else 1e-7)
