@@ -20,13 +20,28 @@ namespace fld {
 namespace {
 
 constexpr int kWave = 64;
+// Index of a cell -> (i, j, k).  Cells number fewer than 2^31 and every
+// axis fewer than 2^16, so (c + 1/2) * (1/nz) in FP64 lies at least 2^-17
+// away from an integer while its rounding error stays below 2^-21: the
+// truncation is the exact quotient.  This avoids 64-bit integer division.
+struct Dec {
+    double inv_ny, inv_nz;
+    int ny, nz;
+    __device__ Dec(int ny_, int nz_) : inv_ny(1.0 / ny_), inv_nz(1.0 / nz_), ny(ny_), nz(nz_) {}
+    __device__ inline void operator()(long long c, int &i, int &j, int &k) const
+    {
+        const unsigned cu = (unsigned)c;
+        const unsigned row = (unsigned)(((double)cu + 0.5) * inv_nz);
+        k = (int)(cu - row * (unsigned)nz);
+        const unsigned ii = (unsigned)(((double)row + 0.5) * inv_ny);
+        j = (int)(row - ii * (unsigned)ny);
+        i = (int)ii;
+    }
+};
 
 __device__ inline void decode(long long c, int ny, int nz, int &i, int &j, int &k)
 {
-    long long row = c / nz;
-    k = (int)(c - row * nz);
-    i = (int)(row / ny);
-    j = (int)(row - (long long)i * ny);
+    Dec(ny, nz)(c, i, j, k);
 }
 
 // Sum of v over the block; the result is valid in thread 0.
@@ -48,22 +63,103 @@ __device__ double block_sum(double v)
 }
 
 // ---------------------------------------------------------------------------
+// Quad access: a thread handles 4 consecutive cells along z (k0 % 4 == 0,
+// nz % 4 == 0), so each array is read with one 16-byte (FP32) or two
+// 16-byte (FP64) loads per neighbour direction.
+// ---------------------------------------------------------------------------
+
+__device__ inline void ld4(const float *p, float v[4])
+{
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ inline void ld4(const double *p, double v[4])
+{
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ inline void ld4(const int *p, int v[4])
+{
+    const int4 t = *reinterpret_cast<const int4 *>(p);
+    v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+}
+__device__ inline void st4(float *p, const float v[4])
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void st4(double *p, const double v[4])
+{
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
+}
+
+// The 7-point neighbourhood of a quad: centre values, the four in-plane /
+// out-of-plane neighbour quads, and the single cells before and after it
+// along z.  `G` is the value used for ghost cells (callers fill ghost quads
+// themselves when the ghost depends on the cell).
+template <typename V>
+struct Hood {
+    V c[4], xm[4], xp[4], ym[4], yp[4];
+    V zl, zr;
+    __device__ V zm(int m) const { return m == 0 ? zl : c[m - 1]; }
+    __device__ V zp(int m) const { return m == 3 ? zr : c[m + 1]; }
+};
+
+// Fill a Hood from quad/single loaders; ghost quads take `ghost`.
+template <typename V, typename L4, typename L1>
+__device__ inline void gather(Hood<V> &h, L4 ld4f, L1 ld1f, long long c0, int i, int j, int k0,
+                              int nx, int ny, int nz, long long sx, long long sy, V ghost)
+{
+    ld4f(c0, h.c);
+    if (i > 0) ld4f(c0 - sx, h.xm); else for (int m = 0; m < 4; ++m) h.xm[m] = ghost;
+    if (i < nx - 1) ld4f(c0 + sx, h.xp); else for (int m = 0; m < 4; ++m) h.xp[m] = ghost;
+    if (j > 0) ld4f(c0 - sy, h.ym); else for (int m = 0; m < 4; ++m) h.ym[m] = ghost;
+    if (j < ny - 1) ld4f(c0 + sy, h.yp); else for (int m = 0; m < 4; ++m) h.yp[m] = ghost;
+    h.zl = k0 > 0 ? ld1f(c0 - 1) : ghost;
+    h.zr = k0 + 4 < nz ? ld1f(c0 + 4) : ghost;
+}
+
+// Face coefficients of the four cells of a quad from cell coefficients
+// (finest level): F = (D_p + D_s)/2, ghost coefficient dghost or (mirror) D_p.
+// Order of the six faces: x-, x+, y-, y+, z-, z+.
+template <typename V>
+__device__ inline void quad_faces(const Hood<V> &D, int i, int j, int k0, int nx, int ny, int nz,
+                                  bool mirror, V dghost, int m, V F[6])
+{
+    const V Dc = D.c[m];
+    const V gD = mirror ? Dc : dghost;
+    F[0] = (V)0.5 * (Dc + (i > 0 ? D.xm[m] : gD));
+    F[1] = (V)0.5 * (Dc + (i < nx - 1 ? D.xp[m] : gD));
+    F[2] = (V)0.5 * (Dc + (j > 0 ? D.ym[m] : gD));
+    F[3] = (V)0.5 * (Dc + (j < ny - 1 ? D.yp[m] : gD));
+    F[4] = (V)0.5 * (Dc + (k0 + m > 0 ? D.zm(m) : gD));
+    F[5] = (V)0.5 * (Dc + (k0 + m < nz - 1 ? D.zp(m) : gD));
+}
+
+// ---------------------------------------------------------------------------
 // Flux limiters F(R), Sec. 4 Table 2.
 // ---------------------------------------------------------------------------
 
 // Levermore-Pomraning (coth R - 1/R)/R.  For R < 2 the subtraction cancels;
 // there the value comes from the continued fraction of coth (Lambert):
-// coth R - 1/R = R/(3 + R^2/(5 + R^2/(7 + ...))), cut at the partial
-// denominator 25.  Above, coth R = 1 + 2/expm1(2R).
+// coth R - 1/R = R/(3 + R^2/(5 + R^2/(7 + ...))), so
+// F = 1/(3 + R^2/(5 + ... + R^2/25)).  Its convergents P_m/Q_m follow the
+// forward three-term recurrence X_m = (2m+3) X_{m-1} + R^2 X_{m-2} (all
+// terms positive, hence stable), which leaves a single division.  Above
+// R = 2, coth R = 1 + 2/expm1(2R).
 __device__ inline double limiter_lp(double R)
 {
     if (R < 2.0) {
         const double x = R * R;
-        double t = 25.0;
+        double p0 = 1.0, p1 = 3.0, q0 = 0.0, q1 = 1.0;
 #pragma unroll
-        for (int m = 11; m >= 1; --m)
-            t = (double)(2 * m + 1) + x / t;
-        return 1.0 / t;
+        for (int m = 1; m <= 11; ++m) {
+            const double b = (double)(2 * m + 3);
+            const double p2 = b * p1 + x * p0, q2 = b * q1 + x * q0;
+            p0 = p1; p1 = p2; q0 = q1; q1 = q2;
+        }
+        return q1 / p1;
     }
     const double coth = 1.0 + 2.0 / expm1(2.0 * R);
     return (coth - 1.0 / R) / R;
@@ -155,16 +251,66 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
         const Fine &f = fines[tk.grid];
         if (active && !active[f.prob])
             continue;
-        const double *phi = f.phi[src];
-        const T *dir = (const T *)f.p[dir_idx];
+        const double *__restrict__ phi = f.phi[src];
+        const T *__restrict__ dir = (const T *)f.p[dir_idx];
+        const double *__restrict__ sig_hat = f.sig_hat;
+        double *__restrict__ phi_out = f.phi[dst];
+        float *__restrict__ D32 = (float *)f.D0;
         const double theta = use_dir ? scal[f.prob * S_COUNT + S_THETA] : 0.0;
         const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
-        double *Dout = to_tmp ? f.Dtmp : f.D64;
+        double *__restrict__ Dout = to_tmp ? f.Dtmp : f.D64;
+        const Dec dec(f.ny, f.nz);
+        if ((f.nz & 3) == 0) {
+            auto L4 = [&](long long x, double v[4]) {
+                ld4(phi + x, v);
+                if (use_dir) {
+                    T pv[4];
+                    ld4(dir + x, pv);
+                    for (int m = 0; m < 4; ++m)
+                        v[m] = v[m] + theta * (double)pv[m];
+                }
+            };
+            auto L1 = [&](long long x) {
+                double v = phi[x];
+                if (use_dir)
+                    v = v + theta * (double)dir[x];
+                return v;
+            };
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                Hood<double> P;
+                gather(P, L4, L1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, f.phi_b);
+                double sh[4], Rq[4], Dq[4];
+                float D32q[4];
+                ld4(sig_hat + c0, sh);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const double dx = P.xp[m] - P.xm[m], dy = P.yp[m] - P.ym[m];
+                    const double dz = P.zp(m) - P.zm(m);
+                    const double grad = sqrt(dx * dx + dy * dy + dz * dz) / (2.0 * f.h);
+                    Rq[m] = fmax(grad, floor_) / fmax(sh[m] * P.c[m], floor_);
+                }
+                if (use_dir && dst != src)
+                    st4(phi_out + c0, P.c);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    Dq[m] = limiter(f.limiter, Rq[m], f.larsen_n) / sh[m];
+                    D32q[m] = (float)Dq[m];
+                }
+                st4(Dout + c0, Dq);
+                if (!to_tmp && sizeof(T) == 4)
+                    st4(D32 + c0, D32q);
+            }
+            continue;
+        }
+#pragma unroll 2
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
-            decode(c, f.ny, f.nz, i, j, k);
+            dec(c, i, j, k);
             auto val = [&](long long x) {
                 double v = phi[x];
                 if (use_dir)
@@ -180,14 +326,14 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
             const double zp = k < f.nz - 1 ? val(c + 1) : f.phi_b;
             const double dx = xp - xm, dy = yp - ym, dz = zp - zm;
             const double grad = sqrt(dx * dx + dy * dy + dz * dz) / (2.0 * f.h);
-            const double sh = f.sig_hat[c];
+            const double sh = sig_hat[c];
             const double R = fmax(grad, floor_) / fmax(sh * pc, floor_);
             const double D = limiter(f.limiter, R, f.larsen_n) / sh;
             Dout[c] = D;
             if (!to_tmp && sizeof(T) == 4)
-                ((float *)f.D0)[c] = (float)D;
+                D32[c] = (float)D;
             if (use_dir && dst != src)
-                f.phi[dst][c] = pc;
+                phi_out[c] = pc;
         }
     }
 }
@@ -209,19 +355,60 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
                 partials[t] = 0.0;
             continue;
         }
-        const double *phi = f.phi[src];
-        const double *D = use_tmp ? f.Dtmp : f.D64;
-        T *b0 = (T *)f.b0[b0_idx];
+        const double *__restrict__ phi = f.phi[src];
+        const double *__restrict__ D = use_tmp ? f.Dtmp : f.D64;
+        const double *__restrict__ jsrc = f.j;
+        const double *__restrict__ sa = f.sa64;
+        T *__restrict__ b0 = (T *)f.b0[b0_idx];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         double acc = 0.0;
+        const Dec dec(f.ny, f.nz);
+        if ((f.nz & 3) == 0) {
+            auto P4 = [&](long long x, double v[4]) { ld4(phi + x, v); };
+            auto P1 = [&](long long x) { return phi[x]; };
+            auto D4 = [&](long long x, double v[4]) { ld4(D + x, v); };
+            auto D1 = [&](long long x) { return D[x]; };
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                Hood<double> P, Dh;
+                gather(P, P4, P1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, f.phi_b);
+                gather(Dh, D4, D1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, f.dghost);
+                double jq[4], saq[4], rq[4];
+                T bq[4];
+                ld4(jsrc + c0, jq);
+                ld4(sa + c0, saq);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    double F[6];
+                    quad_faces(Dh, i, j, k0, f.nx, f.ny, f.nz, f.mirror != 0, f.dghost, m, F);
+                    double num = jq[m] * f.h2;
+                    double den = saq[m] * f.h2;
+                    num = num + F[0] * P.xm[m]; den = den + F[0];
+                    num = num + F[1] * P.xp[m]; den = den + F[1];
+                    num = num + F[2] * P.ym[m]; den = den + F[2];
+                    num = num + F[3] * P.yp[m]; den = den + F[3];
+                    num = num + F[4] * P.zm(m); den = den + F[4];
+                    num = num + F[5] * P.zp(m); den = den + F[5];
+                    rq[m] = (num - P.c[m] * den) / f.h2;
+                    bq[m] = (T)rq[m];
+                    acc += rq[m] * rq[m];
+                }
+                st4(b0 + c0, bq);
+                if (r_out)
+                    st4(r_out + c0, rq);
+            }
+        } else
+#pragma unroll 2
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
-            decode(c, f.ny, f.nz, i, j, k);
+            dec(c, i, j, k);
             const double Dc = D[c];
             const double gD = f.mirror ? Dc : f.dghost;
-            double num = f.j[c] * f.h2;
-            double den = f.sa64[c] * f.h2;
+            double num = jsrc[c] * f.h2;
+            double den = sa[c] * f.h2;
             double F;
             F = 0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
             num = num + F * (i > 0 ? phi[c - sx] : f.phi_b);
@@ -269,6 +456,30 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
         const T *bp = (const T *)f.b0[b0_idx ^ 1];
         T *e = (T *)f.e0;
         double g = 0.0, sg = 0.0;
+        if ((f.nz & 3) == 0) {
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                T eq[4], bq[4], bpq[4];
+                ld4(e + c0, eq);
+                ld4(b + c0, bq);
+                ld4(bp + c0, bpq);
+                if (alpha) {
+                    int lq[4];
+                    ld4(f.label + c0, lq);
+                    if (lq[0] >= 0 || lq[1] >= 0 || lq[2] >= 0 || lq[3] >= 0) {
+                        for (int m = 0; m < 4; ++m)
+                            if (lq[m] >= 0)
+                                eq[m] = (T)(alpha[f.cbase + lq[m]] + (double)eq[m]);
+                        st4(e + c0, eq);
+                    }
+                }
+                for (int m = 0; m < 4; ++m) {
+                    const double ev = (double)eq[m];
+                    g += (double)bq[m] * ev;
+                    sg += ev * (double)bpq[m];
+                }
+            }
+        } else
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             double ev = (double)e[c];
@@ -305,24 +516,70 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
         const Fine &f = fines[tk.grid];
         if (active && !active[f.prob])
             continue;
-        const T *e = (const T *)f.e0;
-        const T *po = (const T *)f.p[pin];
-        T *pn = (T *)f.p[pout];
-        const T *b = (const T *)f.b0[b0_idx];
-        const double *D = f.D64;
+        const T *__restrict__ e = (const T *)f.e0;
+        const T *__restrict__ po = (const T *)f.p[pin];
+        T *__restrict__ pn = (T *)f.p[pout];
+        const T *__restrict__ b = (const T *)f.b0[b0_idx];
+        const double *__restrict__ D = f.D64;
+        const double *__restrict__ sa = f.sa64;
         const double beta = scal[f.prob * S_COUNT + S_BETA];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         double arp = 0.0, apap = 0.0;
+        const Dec dec(f.ny, f.nz);
+        if ((f.nz & 3) == 0) {
+            auto P4 = [&](long long x, double v[4]) {
+                T ev[4], pv[4];
+                ld4(e + x, ev);
+                ld4(po + x, pv);
+                for (int m = 0; m < 4; ++m)
+                    v[m] = (double)(T)((double)ev[m] + beta * (double)pv[m]);
+            };
+            auto P1 = [&](long long x) { return (double)(T)((double)e[x] + beta * (double)po[x]); };
+            auto D4 = [&](long long x, double v[4]) { ld4(D + x, v); };
+            auto D1 = [&](long long x) { return D[x]; };
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                Hood<double> P, Dh;
+                gather(P, P4, P1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, 0.0);
+                gather(Dh, D4, D1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, f.dghost);
+                double saq[4];
+                T bq[4], pq[4];
+                ld4(sa + c0, saq);
+                ld4(b + c0, bq);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    double F[6];
+                    quad_faces(Dh, i, j, k0, f.nx, f.ny, f.nz, f.mirror != 0, f.dghost, m, F);
+                    double nb = 0.0;
+                    double den = saq[m] * f.h2;
+                    nb = nb + F[0] * P.xm[m]; den = den + F[0];
+                    nb = nb + F[1] * P.xp[m]; den = den + F[1];
+                    nb = nb + F[2] * P.ym[m]; den = den + F[2];
+                    nb = nb + F[3] * P.yp[m]; den = den + F[3];
+                    nb = nb + F[4] * P.zm(m); den = den + F[4];
+                    nb = nb + F[5] * P.zp(m); den = den + F[5];
+                    const double pc = P.c[m];
+                    const double Ap = (pc * den - nb) / f.h2;
+                    pq[m] = (T)pc;
+                    arp += (double)bq[m] * pc;
+                    apap += pc * Ap;
+                }
+                st4(pn + c0, pq);
+            }
+        } else
+#pragma unroll 2
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
-            decode(c, f.ny, f.nz, i, j, k);
+            dec(c, i, j, k);
             auto pv = [&](long long x) { return (double)(T)((double)e[x] + beta * (double)po[x]); };
             const double Dc = D[c];
             const double gD = f.mirror ? Dc : f.dghost;
             const double pc = pv(c);
             double nb = 0.0;
-            double den = f.sa64[c] * f.h2;
+            double den = sa[c] * f.h2;
             double F;
             F = 0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
             nb = nb + F * (i > 0 ? pv(c - sx) : 0.0);
@@ -381,10 +638,11 @@ k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, in
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         const double gD0 = (double)(T)f.dghost;
         double ad = 0.0, as = 0.0;
+        const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = f.ccells[tk.start + q];
             int i, j, k;
-            decode(c, f.ny, f.nz, i, j, k);
+            dec(c, i, j, k);
             const int lc = lab[c];
             const double Dc = (double)D[c];
             const double gD = f.mirror ? Dc : gD0;
@@ -445,18 +703,19 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
         const Fine &f = fines[tk.grid];
         if (active && !active[f.prob])
             continue;
-        const T *D = (const T *)f.D0;
-        const T *sa = (const T *)f.sa0;
-        const T *b = (const T *)f.b0[b0_idx];
-        T *b1 = (T *)f.b1;
-        const int *lab = f.label;
-        const double *al = alpha + f.cbase;
+        const T *__restrict__ D = (const T *)f.D0;
+        const T *__restrict__ sa = (const T *)f.sa0;
+        const T *__restrict__ b = (const T *)f.b0[b0_idx];
+        T *__restrict__ b1 = (T *)f.b1;
+        const int *__restrict__ lab = f.label;
+        const double *__restrict__ al = alpha + f.cbase;
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         const double gD0 = (double)(T)f.dghost;
+        const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
-            decode(c, f.ny, f.nz, i, j, k);
+            dec(c, i, j, k);
             auto ev = [&](bool in, long long x) {
                 if (!in)
                     return 0.0;
@@ -517,10 +776,11 @@ k_alg1_pass(const Fine *fines, const Task *tasks, int ntasks, const double *scal
         const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         double acc = 0.0;
+        const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
-            decode(c, f.ny, f.nz, i, j, k);
+            dec(c, i, j, k);
             if (((i + j + k) & 1) != colour)
                 continue;
             const double pc = phi[c];
@@ -657,38 +917,89 @@ __device__ inline T face_below(const Grid &g, int ax, int i, int j, int k)
     return (T)0.5 * (Din + (g.mirror ? Din : (T)g.dghost));
 }
 
-// num = b h^2 + sum_s F_s e_s, den = sa h^2 + sum_s F_s (ghost e = 0).
+// num = b h^2 + sum_s F_s e_s, den = sa h^2 + sum_s F_s (ghost e = 0),
+// neighbours in the order x-, x+, y-, y+, z-, z+.  Finest level: faces from
+// the cell coefficients, (D_p + D_s)/2, ghost coefficient eps*h or D_p.
 template <typename T>
-__device__ inline void level_num_den(const Grid &g, const T *e, long long c, int i, int j, int k,
-                                     T &num, T &den)
+__device__ inline void cell_num_den(const Grid &g, const T *e, long long c, int i,
+                                    int j, int k, T &num, T &den)
 {
     const T h2 = (T)g.h2;
-    const T *sa = (const T *)g.sa;
-    const T *b = (const T *)g.b;
+    const T *__restrict__ D = (const T *)g.D;
     const long long sx = (long long)g.ny * g.nz, sy = g.nz;
-    T n_ = b[c] * h2;
-    T d_ = sa[c] * h2;
+    const T Dc = D[c];
+    const T gD = g.mirror ? Dc : (T)g.dghost;
+    T n_ = ((const T *)g.b)[c] * h2;
+    T d_ = ((const T *)g.sa)[c] * h2;
     T F;
-    F = face_below<T>(g, 0, i, j, k);
+    F = (T)0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
     n_ = n_ + F * (i > 0 ? e[c - sx] : (T)0);
     d_ = d_ + F;
-    F = face_below<T>(g, 0, i + 1, j, k);
+    F = (T)0.5 * (Dc + (i < g.nx - 1 ? D[c + sx] : gD));
     n_ = n_ + F * (i < g.nx - 1 ? e[c + sx] : (T)0);
     d_ = d_ + F;
-    F = face_below<T>(g, 1, i, j, k);
+    F = (T)0.5 * (Dc + (j > 0 ? D[c - sy] : gD));
     n_ = n_ + F * (j > 0 ? e[c - sy] : (T)0);
     d_ = d_ + F;
-    F = face_below<T>(g, 1, i, j + 1, k);
+    F = (T)0.5 * (Dc + (j < g.ny - 1 ? D[c + sy] : gD));
     n_ = n_ + F * (j < g.ny - 1 ? e[c + sy] : (T)0);
     d_ = d_ + F;
-    F = face_below<T>(g, 2, i, j, k);
+    F = (T)0.5 * (Dc + (k > 0 ? D[c - 1] : gD));
     n_ = n_ + F * (k > 0 ? e[c - 1] : (T)0);
     d_ = d_ + F;
-    F = face_below<T>(g, 2, i, j, k + 1);
+    F = (T)0.5 * (Dc + (k < g.nz - 1 ? D[c + 1] : gD));
     n_ = n_ + F * (k < g.nz - 1 ? e[c + 1] : (T)0);
     d_ = d_ + F;
     num = n_;
     den = d_;
+}
+
+// Coarse level: Galerkin face coefficients f[axis] on the padded grid.
+template <typename T>
+__device__ inline void face_num_den(const Grid &g, const T *e, long long c, int i,
+                                    int j, int k, T &num, T &den)
+{
+    const T h2 = (T)g.h2;
+    const long long sx = (long long)g.ny * g.nz, sy = g.nz;
+    const long long fy = (long long)(g.nz + 1), fx = (long long)(g.ny + 1) * fy;
+    const long long nf = (long long)(g.nx + 1) * fx;
+    const long long fi = (long long)i * fx + (long long)j * fy + k;
+    const T *__restrict__ Fx = (const T *)g.f;
+    const T *__restrict__ Fy = Fx + nf;
+    const T *__restrict__ Fz = Fy + nf;
+    T n_ = ((const T *)g.b)[c] * h2;
+    T d_ = ((const T *)g.sa)[c] * h2;
+    T F;
+    F = Fx[fi];
+    n_ = n_ + F * (i > 0 ? e[c - sx] : (T)0);
+    d_ = d_ + F;
+    F = Fx[fi + fx];
+    n_ = n_ + F * (i < g.nx - 1 ? e[c + sx] : (T)0);
+    d_ = d_ + F;
+    F = Fy[fi];
+    n_ = n_ + F * (j > 0 ? e[c - sy] : (T)0);
+    d_ = d_ + F;
+    F = Fy[fi + fy];
+    n_ = n_ + F * (j < g.ny - 1 ? e[c + sy] : (T)0);
+    d_ = d_ + F;
+    F = Fz[fi];
+    n_ = n_ + F * (k > 0 ? e[c - 1] : (T)0);
+    d_ = d_ + F;
+    F = Fz[fi + 1];
+    n_ = n_ + F * (k < g.nz - 1 ? e[c + 1] : (T)0);
+    d_ = d_ + F;
+    num = n_;
+    den = d_;
+}
+
+template <typename T>
+__device__ inline void level_num_den(const Grid &g, const T *e, long long c, int i, int j, int k,
+                                     T &num, T &den)
+{
+    if (g.fine)
+        cell_num_den<T>(g, e, c, i, j, k, num, den);
+    else
+        face_num_den<T>(g, e, c, i, j, k, num, den);
 }
 
 template <typename T>
@@ -707,7 +1018,9 @@ k_zero(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 }
 
 // One red-black Gauss-Seidel half-sweep (in place: a colour reads only the
-// other colour): e_p <- w num/den + (1-w) e_p.
+// other colour): e_p <- w num/den + (1-w) e_p.  Smoothed levels have even
+// dimensions; a task's cells pair up along z and each thread updates the
+// cell of the requested colour in its pair.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour, T omega)
@@ -718,15 +1031,70 @@ k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, in
         if (active && !active[g.prob])
             continue;
         T *e = (T *)g.e;
-        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
-            const long long c = tk.start + q;
-            int i, j, k;
-            decode(c, g.ny, g.nz, i, j, k);
-            if (((i + j + k) & 1) != colour)
-                continue;
-            T num, den;
-            level_num_den<T>(g, e, c, i, j, k, num, den);
-            e[c] = omega * (num / den) + ((T)1 - omega) * e[c];
+        const Dec dec(g.ny, g.nz);
+        const int npairs = tk.count >> 1;
+        if (g.fine && (g.nz & 3) == 0) {
+            const T *__restrict__ D = (const T *)g.D;
+            const T *__restrict__ bb = (const T *)g.b;
+            const T *__restrict__ sa = (const T *)g.sa;
+            const long long sx = (long long)g.ny * g.nz, sy = g.nz;
+            const T h2 = (T)g.h2;
+            auto E4 = [&](long long x, T v[4]) { ld4(e + x, v); };
+            auto E1 = [&](long long x) { return e[x]; };
+            auto D4 = [&](long long x, T v[4]) { ld4(D + x, v); };
+            auto D1 = [&](long long x) { return D[x]; };
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                Hood<T> Eh, Dh;
+                gather(Eh, E4, E1, c0, i, j, k0, g.nx, g.ny, g.nz, sx, sy, (T)0);
+                gather(Dh, D4, D1, c0, i, j, k0, g.nx, g.ny, g.nz, sx, sy, (T)g.dghost);
+                T bq[4], saq[4], out[4];
+                ld4(bb + c0, bq);
+                ld4(sa + c0, saq);
+                const int first = (i + j + colour) & 1;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    out[m] = Eh.c[m];
+                    if ((m & 1) != first)
+                        continue;
+                    T F[6];
+                    quad_faces(Dh, i, j, k0, g.nx, g.ny, g.nz, g.mirror != 0, (T)g.dghost, m, F);
+                    T n_ = bq[m] * h2;
+                    T d_ = saq[m] * h2;
+                    n_ = n_ + F[0] * Eh.xm[m]; d_ = d_ + F[0];
+                    n_ = n_ + F[1] * Eh.xp[m]; d_ = d_ + F[1];
+                    n_ = n_ + F[2] * Eh.ym[m]; d_ = d_ + F[2];
+                    n_ = n_ + F[3] * Eh.yp[m]; d_ = d_ + F[3];
+                    n_ = n_ + F[4] * Eh.zm(m); d_ = d_ + F[4];
+                    n_ = n_ + F[5] * Eh.zp(m); d_ = d_ + F[5];
+                    out[m] = omega * (n_ / d_) + ((T)1 - omega) * Eh.c[m];
+                }
+                st4(e + c0, out);
+            }
+        } else if (g.fine) {
+            for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
+                const long long c0 = tk.start + 2 * (long long)q;
+                int i, j, k;
+                dec(c0, i, j, k);
+                const int odd = (i + j + colour) & 1;
+                const long long c = c0 + odd;
+                T num, den;
+                cell_num_den<T>(g, e, c, i, j, k + odd, num, den);
+                e[c] = omega * (num / den) + ((T)1 - omega) * e[c];
+            }
+        } else {
+            for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
+                const long long c0 = tk.start + 2 * (long long)q;
+                int i, j, k;
+                dec(c0, i, j, k);
+                const int odd = (i + j + colour) & 1;
+                const long long c = c0 + odd;
+                T num, den;
+                face_num_den<T>(g, e, c, i, j, k + odd, num, den);
+                e[c] = omega * (num / den) + ((T)1 - omega) * e[c];
+            }
         }
     }
 }
@@ -746,10 +1114,11 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         const T *e = (const T *)F.e;
         T *bc = (T *)C.b;
         const T h2 = (T)F.h2;
+        const Dec dec(C.ny, C.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long cc = tk.start + q;
             int I, J, K;
-            decode(cc, C.ny, C.nz, I, J, K);
+            dec(cc, I, J, K);
             T s = (T)0;
             for (int di = 0; di < 2; ++di)
                 for (int dj = 0; dj < 2; ++dj)
@@ -778,10 +1147,11 @@ k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         const Grid &C = grids[F.coarser];
         T *ef = (T *)F.e;
         const T *ec = (const T *)C.e;
+        const Dec dec(F.ny, F.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
-            decode(c, F.ny, F.nz, i, j, k);
+            dec(c, i, j, k);
             ef[c] = ef[c] + ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
         }
     }
@@ -802,10 +1172,11 @@ k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         const Grid &F = grids[C.finer];
         T *fc = (T *)C.f;
         const long long nf = (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
+        const Dec dec(C.ny + 1, C.nz + 1);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int I, J, K;
-            decode(c, C.ny + 1, C.nz + 1, I, J, K);
+            dec(c, I, J, K);
             // x faces
             T v = (T)0;
             if (J < C.ny && K < C.nz) {
@@ -851,10 +1222,11 @@ k_mean8_sa(const Grid *grids, const Task *tasks, int ntasks)
         const Grid &F = grids[C.finer];
         const T *sf = (const T *)F.sa;
         T *sc = (T *)C.sa;
+        const Dec dec(C.ny, C.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long cc = tk.start + q;
             int I, J, K;
-            decode(cc, C.ny, C.nz, I, J, K);
+            dec(cc, I, J, K);
             T s = (T)0;
             for (int di = 0; di < 2; ++di)
                 for (int dj = 0; dj < 2; ++dj)
@@ -867,25 +1239,33 @@ k_mean8_sa(const Grid *grids, const Task *tasks, int ntasks)
 
 // Coarsest level: banded Cholesky of M = h^2 A (natural order, half
 // bandwidth bw = ny*nz), FP64.  Band entry (r, q), r - bw <= q <= r, sits at
-// band[r*(bw+1) + q - r + bw].
+// band[r*(bw+1) + q - r + bw].  Right-looking: after column c is scaled,
+// every entry of the trailing band subtracts L(r,c) L(q,c); each entry thus
+// receives its subtractions in ascending column order, the order of the
+// textbook (left-looking) recurrence.  The band is factored in LDS when it
+// fits (kCholLds bytes) and in global memory otherwise.
+constexpr int kCholLds = 64 * 1024;
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_chol_factor(const Grid *grids, const int *ids, const int *active, int *fail)
 {
+    extern __shared__ double lds[];
     const Grid &g = grids[ids[blockIdx.x]];
     if (active && !active[g.prob])
         return;
     const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
-    double *L = g.band;
+    const bool in_lds = (long long)n * W * 8 <= kCholLds;
+    double *L = in_lds ? lds : g.band;
     const double h2 = g.h2;
     const T *sa = (const T *)g.sa;
-    // assemble the lower band of M
+    const Dec dec(g.ny, g.nz);
     for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x) {
         const int r = (int)(x / W), d = (int)(x - (long long)r * W);
         const int q = r - bw + d;
         double v = 0.0;
         int i, j, k;
-        decode(r, g.ny, g.nz, i, j, k);
+        dec(r, i, j, k);
         if (q == r) {
             v = (double)sa[r] * h2;
             v = v + (double)face_below<T>(g, 0, i, j, k);
@@ -905,75 +1285,91 @@ k_chol_factor(const Grid *grids, const int *ids, const int *active, int *fail)
         }
         L[x] = v;
     }
-    __syncthreads();
     __shared__ int bad;
     if (threadIdx.x == 0)
         bad = 0;
     __syncthreads();
     for (int c = 0; c < n; ++c) {
         if (threadIdx.x == 0) {
-            double d = L[(long long)c * W + bw];
-            for (int q = (c - bw > 0 ? c - bw : 0); q < c; ++q) {
-                const double l = L[(long long)c * W + q - c + bw];
-                d = d - l * l;
-            }
+            const double d = L[(long long)c * W + bw];
             if (!(d > 0.0))
                 bad = 1;
             L[(long long)c * W + bw] = sqrt(d);
         }
         __syncthreads();
         const double lcc = L[(long long)c * W + bw];
-        const int rmax = (c + bw < n - 1) ? c + bw : n - 1;
-        for (int r = c + 1 + threadIdx.x; r <= rmax; r += blockDim.x) {
-            double s = L[(long long)r * W + c - r + bw];
-            for (int q = (r - bw > 0 ? r - bw : 0); q < c; ++q)
-                s = s - L[(long long)r * W + q - r + bw] * L[(long long)c * W + q - c + bw];
-            L[(long long)r * W + c - r + bw] = s / lcc;
+        const int m = (c + bw < n - 1) ? bw : n - 1 - c;   // rows below c in the band
+        for (int a = threadIdx.x; a < m; a += blockDim.x) {
+            const int r = c + 1 + a;
+            L[(long long)r * W + c - r + bw] = L[(long long)r * W + c - r + bw] / lcc;
+        }
+        __syncthreads();
+        for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
+            const int a = x / m, b = x - a * m;      // r = c+1+a, q = c+1+b, q <= r
+            if (b > a)
+                continue;
+            const int r = c + 1 + a, q = c + 1 + b;
+            const double lrc = L[(long long)r * W + c - r + bw];
+            const double lqc = L[(long long)q * W + c - q + bw];
+            double &t = L[(long long)r * W + q - r + bw];
+            t = t - lrc * lqc;
         }
         __syncthreads();
     }
+    if (in_lds)
+        for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x)
+            g.band[x] = L[x];
     if (threadIdx.x == 0 && bad)
         fail[g.prob] = 1;
 }
 
-// Forward/backward substitution with the band factor; the inner products
-// are split over the first wave and reduced with shuffles.
+// Forward/backward substitution with the band factor (staged in LDS when it
+// fits); the inner products are split over the first wave and reduced with
+// shuffles.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_chol_solve(const Grid *grids, const int *ids, const int *active)
+k_chol_solve(const Grid *grids, const int *ids, const int *active, int max_n)
 {
-    extern __shared__ double y[];
+    extern __shared__ double lds[];
     const Grid &g = grids[ids[blockIdx.x]];
     if (active && !active[g.prob])
         return;
     const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
-    const double *L = g.band;
+    double *y = lds;
+    const bool in_lds = (long long)n * W * 8 + (long long)max_n * 8 <= kCholLds;
+    double *L = in_lds ? lds + max_n : g.band;
+    if (in_lds)
+        for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x)
+            L[x] = g.band[x];
     const T *b = (const T *)g.b;
     T *e = (T *)g.e;
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+        y[r] = (double)b[r] * g.h2;
+    __syncthreads();
     const int lane = threadIdx.x;
     for (int r = 0; r < n; ++r) {
-        double part = 0.0;
-        if (lane < kWave)
+        if (lane < kWave) {
+            double part = 0.0;
             for (int q = (r - bw > 0 ? r - bw : 0) + lane; q < r; q += kWave)
                 part += L[(long long)r * W + q - r + bw] * y[q];
-        if (lane < kWave)
             for (int o = kWave / 2; o > 0; o >>= 1)
                 part += __shfl_xor(part, o, kWave);
-        if (lane == 0)
-            y[r] = ((double)b[r] * g.h2 - part) / L[(long long)r * W + bw];
+            if (lane == 0)
+                y[r] = (y[r] - part) / L[(long long)r * W + bw];
+        }
         __syncthreads();
     }
     for (int r = n - 1; r >= 0; --r) {
-        double part = 0.0;
-        const int qmax = (r + bw < n - 1) ? r + bw : n - 1;
-        if (lane < kWave)
+        if (lane < kWave) {
+            double part = 0.0;
+            const int qmax = (r + bw < n - 1) ? r + bw : n - 1;
             for (int q = r + 1 + lane; q <= qmax; q += kWave)
                 part += L[(long long)q * W + r - q + bw] * y[q];
-        if (lane < kWave)
             for (int o = kWave / 2; o > 0; o >>= 1)
                 part += __shfl_xor(part, o, kWave);
-        if (lane == 0)
-            y[r] = (y[r] - part) / L[(long long)r * W + bw];
+            if (lane == 0)
+                y[r] = (y[r] - part) / L[(long long)r * W + bw];
+        }
         __syncthreads();
     }
     for (int r = threadIdx.x; r < n; r += blockDim.x)
@@ -1180,8 +1576,8 @@ void launch_chol_factor(hipStream_t s, const Grid *grids, const int *ids, int co
                         const int *active, int *fail)
 {
     if (count > 0)
-        hipLaunchKernelGGL(k_chol_factor<T>, dim3(count), dim3(kBlock), 0, s, grids, ids, active,
-                           fail);
+        hipLaunchKernelGGL(k_chol_factor<T>, dim3(count), dim3(kBlock), kCholLds, s, grids, ids,
+                           active, fail);
 }
 
 template <typename T>
@@ -1189,8 +1585,8 @@ void launch_chol_solve(hipStream_t s, const Grid *grids, const int *ids, int cou
                        const int *active, int max_n)
 {
     if (count > 0)
-        hipLaunchKernelGGL(k_chol_solve<T>, dim3(count), dim3(kBlock), sizeof(double) * max_n, s,
-                           grids, ids, active);
+        hipLaunchKernelGGL(k_chol_solve<T>, dim3(count), dim3(kBlock), kCholLds, s, grids, ids,
+                           active, max_n);
 }
 
 #define FLD_INSTANTIATE(T)                                                                       \
