@@ -512,6 +512,7 @@ struct fld_engine_impl {
         };
         std::vector<int> vK(vols.size());
         std::vector<int *> vlabel(vols.size()), vcells(vols.size());
+        std::vector<unsigned short *> vmask(vols.size());
         std::vector<std::vector<int>> vstart(vols.size());
         for (size_t v = 0; v < vols.size(); ++v) {
             const Vol &V = vols[v];
@@ -532,8 +533,29 @@ struct fld_engine_impl {
             for (long long c = 0; c < V.n; ++c)
                 if (label[c] >= 0)
                     cells[fill[label[c]]++] = (int)c;
+            // faces leaving the cluster, in the order x-, x+, y-, y+, z-, z+
+            std::vector<unsigned short> mask(cells.size());
+            const long long sx = (long long)V.ny * V.nz, sy = V.nz;
+            for (size_t q = 0; q < cells.size(); ++q) {
+                const long long c = cells[q];
+                const int k = (int)(c % V.nz), j = (int)((c / V.nz) % V.ny), i = (int)(c / sx);
+                const bool in[6] = {i > 0, i < V.nx - 1, j > 0, j < V.ny - 1, k > 0, k < V.nz - 1};
+                const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
+                unsigned short mk = 0;
+                for (int d = 0; d < 6; ++d) {
+                    if (!in[d])
+                        mk |= (unsigned short)((1u << d) | (1u << (d + 6)));
+                    else if (label[c + off[d]] != label[c])
+                        mk |= (unsigned short)(1u << d);
+                }
+                mask[q] = mk;
+            }
             CK(dal((void **)&vlabel[v], sizeof(int) * V.n));
             CK(dal((void **)&vcells[v], sizeof(int) * cells.size()));
+            CK(dal((void **)&vmask[v], sizeof(unsigned short) * mask.size()));
+            if (!mask.empty())
+                HK(hipMemcpy(vmask[v], mask.data(), sizeof(unsigned short) * mask.size(),
+                             hipMemcpyHostToDevice), "cluster masks");
             HK(hipMemcpy(vlabel[v], label.data(), sizeof(int) * V.n, hipMemcpyHostToDevice), "labels");
             if (!cells.empty())
                 HK(hipMemcpy(vcells[v], cells.data(), sizeof(int) * cells.size(),
@@ -548,6 +570,7 @@ struct fld_engine_impl {
             const int v = probs[p].vol;
             f.label = vlabel[v];
             f.ccells = vcells[v];
+            f.cmask = vmask[v];
             f.cbase = ncl_total;
             f.ncl = vK[v];
             for (int q = 0; q < vK[v]; ++q) {

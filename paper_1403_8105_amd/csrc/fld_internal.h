@@ -52,6 +52,8 @@ struct Fine {
     void *D0, *sa0;      // finest coefficients in precision T
     const int *label;    // cluster of each voxel (-1: none), per volume
     const int *ccells;   // voxels of every cluster, cluster by cluster
+    const unsigned short *cmask;  // per ccells entry: faces leaving the cluster (bits 0-5),
+                                  // of which ghost faces (bits 6-11)
     int cbase;           // first global cluster index of this problem
     int ncl;             // clusters of this problem
     void *b1;            // deflated V-cycle right-hand side (precision T)

@@ -634,31 +634,27 @@ k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, in
         const T *D = (const T *)f.D0;
         const T *sa = (const T *)f.sa0;
         const T *b = (const T *)f.b0[b0_idx];
-        const int *lab = f.label;
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         const double gD0 = (double)(T)f.dghost;
         double ad = 0.0, as = 0.0;
-        const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = f.ccells[tk.start + q];
-            int i, j, k;
-            dec(c, i, j, k);
-            const int lc = lab[c];
-            const double Dc = (double)D[c];
-            const double gD = f.mirror ? Dc : gD0;
+            const int mask = f.cmask[tk.start + q];
             double v = (double)sa[c];
-            auto cut = [&](bool in, long long x) {
-                if (in && lab[x] == lc)
-                    return;
-                const double F = 0.5 * (Dc + (in ? (double)D[x] : gD));
-                v = v + F / f.h2;
-            };
-            cut(i > 0, c - sx);
-            cut(i < f.nx - 1, c + sx);
-            cut(j > 0, c - sy);
-            cut(j < f.ny - 1, c + sy);
-            cut(k > 0, c - 1);
-            cut(k < f.nz - 1, c + 1);
+            if (mask) {
+                // faces leaving the cluster: bit s set for neighbour s
+                // (x-, x+, y-, y+, z-, z+); bit s+6 set when it is a ghost
+                const double Dc = (double)D[c];
+                const double gD = f.mirror ? Dc : gD0;
+                const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
+#pragma unroll
+                for (int d = 0; d < 6; ++d)
+                    if (mask & (1 << d)) {
+                        const bool ghost = (mask >> (d + 6)) & 1;
+                        const double F = 0.5 * (Dc + (ghost ? gD : (double)D[c + off[d]]));
+                        v = v + F / f.h2;
+                    }
+            }
             ad += v;
             as += (double)b[c];
         }
@@ -712,6 +708,63 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         const double gD0 = (double)(T)f.dghost;
         const Dec dec(f.ny, f.nz);
+        if ((f.nz & 3) == 0) {
+            auto A4 = [&](long long x, double v[4]) {
+                int l[4];
+                ld4(lab + x, l);
+                for (int m = 0; m < 4; ++m)
+                    v[m] = l[m] >= 0 ? al[l[m]] : 0.0;
+            };
+            auto A1 = [&](long long x) {
+                const int l = lab[x];
+                return l >= 0 ? al[l] : 0.0;
+            };
+            auto D4 = [&](long long x, double v[4]) {
+                T t[4];
+                ld4(D + x, t);
+                for (int m = 0; m < 4; ++m)
+                    v[m] = (double)t[m];
+            };
+            auto D1 = [&](long long x) { return (double)D[x]; };
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                Hood<double> Eh;
+                gather(Eh, A4, A1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, 0.0);
+                bool any = Eh.zl != 0.0 || Eh.zr != 0.0;
+                for (int m = 0; m < 4; ++m)
+                    any = any || Eh.c[m] != 0.0 || Eh.xm[m] != 0.0 || Eh.xp[m] != 0.0 ||
+                          Eh.ym[m] != 0.0 || Eh.yp[m] != 0.0;
+                T bq[4];
+                ld4(b + c0, bq);
+                if (!any) {
+                    st4(b1 + c0, bq);
+                    continue;
+                }
+                Hood<double> Dh;
+                gather(Dh, D4, D1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, gD0);
+                T saq[4], out[4];
+                ld4(sa + c0, saq);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    double Fc[6];
+                    quad_faces(Dh, i, j, k0, f.nx, f.ny, f.nz, f.mirror != 0, gD0, m, Fc);
+                    double nb = 0.0;
+                    double den = (double)saq[m] * f.h2;
+                    nb = nb + Fc[0] * Eh.xm[m]; den = den + Fc[0];
+                    nb = nb + Fc[1] * Eh.xp[m]; den = den + Fc[1];
+                    nb = nb + Fc[2] * Eh.ym[m]; den = den + Fc[2];
+                    nb = nb + Fc[3] * Eh.yp[m]; den = den + Fc[3];
+                    nb = nb + Fc[4] * Eh.zm(m); den = den + Fc[4];
+                    nb = nb + Fc[5] * Eh.zp(m); den = den + Fc[5];
+                    const double Ae = (Eh.c[m] * den - nb) / f.h2;
+                    out[m] = (T)((double)bq[m] - Ae);
+                }
+                st4(b1 + c0, out);
+            }
+            continue;
+        }
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int i, j, k;
@@ -1115,6 +1168,57 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         T *bc = (T *)C.b;
         const T h2 = (T)F.h2;
         const Dec dec(C.ny, C.nz);
+        if (F.fine && (F.nz & 3) == 0) {
+            // two coarse cells along z per thread: their children form one fine
+            // quad in each of the four (di, dj) rows
+            const T *__restrict__ D = (const T *)F.D;
+            const T *__restrict__ bf = (const T *)F.b;
+            const T *__restrict__ sa = (const T *)F.sa;
+            const long long sx = (long long)F.ny * F.nz, sy = F.nz;
+            auto E4 = [&](long long x, T v[4]) { ld4(e + x, v); };
+            auto E1 = [&](long long x) { return e[x]; };
+            auto D4 = [&](long long x, T v[4]) { ld4(D + x, v); };
+            auto D1 = [&](long long x) { return D[x]; };
+            for (int q = threadIdx.x; q < (tk.count >> 1); q += blockDim.x) {
+                const long long cc = tk.start + 2 * (long long)q;
+                int I, J, K;
+                dec(cc, I, J, K);
+                T s0 = (T)0, s1 = (T)0;
+#pragma unroll 1
+                for (int dd = 0; dd < 4; ++dd) {
+                        const int di = dd >> 1, dj = dd & 1;
+                        const int i = 2 * I + di, j = 2 * J + dj, k0 = 2 * K;
+                        const long long c0 = ((long long)i * F.ny + j) * F.nz + k0;
+                        Hood<T> Eh, Dh;
+                        gather(Eh, E4, E1, c0, i, j, k0, F.nx, F.ny, F.nz, sx, sy, (T)0);
+                        gather(Dh, D4, D1, c0, i, j, k0, F.nx, F.ny, F.nz, sx, sy, (T)F.dghost);
+                        T bq[4], saq[4], r[4];
+                        ld4(bf + c0, bq);
+                        ld4(sa + c0, saq);
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            T Fc[6];
+                            quad_faces(Dh, i, j, k0, F.nx, F.ny, F.nz, F.mirror != 0, (T)F.dghost, m, Fc);
+                            T n_ = bq[m] * h2;
+                            T d_ = saq[m] * h2;
+                            n_ = n_ + Fc[0] * Eh.xm[m]; d_ = d_ + Fc[0];
+                            n_ = n_ + Fc[1] * Eh.xp[m]; d_ = d_ + Fc[1];
+                            n_ = n_ + Fc[2] * Eh.ym[m]; d_ = d_ + Fc[2];
+                            n_ = n_ + Fc[3] * Eh.yp[m]; d_ = d_ + Fc[3];
+                            n_ = n_ + Fc[4] * Eh.zm(m); d_ = d_ + Fc[4];
+                            n_ = n_ + Fc[5] * Eh.zp(m); d_ = d_ + Fc[5];
+                            r[m] = (n_ - Eh.c[m] * d_) / h2;
+                        }
+                        s0 = s0 + r[0];
+                        s0 = s0 + r[1];
+                        s1 = s1 + r[2];
+                        s1 = s1 + r[3];
+                    }
+                bc[cc] = (T)0.125 * s0;
+                bc[cc + 1] = (T)0.125 * s1;
+            }
+            continue;
+        }
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long cc = tk.start + q;
             int I, J, K;
