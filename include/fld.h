@@ -100,6 +100,9 @@ typedef struct fld_options {
                              ((1/3)/sig_p + (1/3)/sig_s)/2 exceeds tau*L form clusters whose
                              constant mode is removed before each V-cycle; <= 0 disables
                              (default 1)                                                  */
+    int graph;            /* multigrid: replay each outer iteration from a captured HIP graph
+                             (two graphs, one per buffer parity; default 1).  Ignored when
+                             timing is set: timed kernels are launched one by one          */
 } fld_options;
 
 typedef struct fld_report {

@@ -34,7 +34,8 @@ class fld_options(C.Structure):
                 ("omega", C.c_double), ("omega_s", C.c_double), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("max_coarsest", C.c_int), ("max_iters", C.c_int),
                 ("tol", C.c_double), ("check_every", C.c_int), ("device", C.c_int),
-                ("stream", C.c_void_p), ("timing", C.c_int), ("deflate_tau", C.c_double)]
+                ("stream", C.c_void_p), ("timing", C.c_int), ("deflate_tau", C.c_double),
+                ("graph", C.c_int)]
 
 
 class fld_report(C.Structure):

@@ -98,19 +98,30 @@ struct fld_engine_impl {
     int k_state = 0;               // next outer iteration index (resume)
     bool solved_once = false;
 
-    // HIP-event timing of the hot kernels (options.timing)
+    // HIP-event timing of the hot kernels (options.timing).  Each interval
+    // carries its algorithmic bytes per active finest cell; intervals recorded
+    // while a graph is captured stay with that graph and are read after every
+    // replay.
     struct Timed {
         hipEvent_t a, b;
         int cls;
-        double bytes;
+        double bytes_per_cell;
     };
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<Timed> timed;
+    std::vector<Timed> timed, *timed_sink = &timed;
+    double acc_ms[4] = {}, acc_launch[4] = {}, acc_bytes[4] = {};
     double fine_cells = 0.0;       // sum of finest-level cells over problems
+    bool capturing = false;
 
     hipEvent_t next_event()
     {
+        if (capturing) {
+            hipEvent_t e = nullptr;
+            hipEventCreate(&e);
+            graph_events.push_back(e);
+            return e;
+        }
         if (ev_used == ev_pool.size()) {
             hipEvent_t e = nullptr;
             hipEventCreate(&e);
@@ -126,28 +137,60 @@ struct fld_engine_impl {
         hipEventRecord(e, stream);
         return e;
     }
-    void toc(hipEvent_t a, int cls, double bytes)
+    void toc(hipEvent_t a, int cls, double bytes_per_cell)
     {
         if (!opt.timing)
             return;
         hipEvent_t b = next_event();
         hipEventRecord(b, stream);
-        timed.push_back(Timed{a, b, cls, bytes});
+        timed_sink->push_back(Timed{a, b, cls, bytes_per_cell});
     }
-    // Sum the recorded intervals (after the stream was synchronised).
-    void collect_timing(double ms[4], double launches[4], double bytes[4])
+    // Add finished intervals to the accumulators (stream synchronised).
+    void harvest(std::vector<Timed> &v, bool clear)
     {
-        for (int q = 0; q < 4; ++q)
-            ms[q] = launches[q] = bytes[q] = 0.0;
-        for (const Timed &t : timed) {
+        const double cells = active_fine_cells();
+        for (const Timed &t : v) {
             float m = 0.0f;
             hipEventElapsedTime(&m, t.a, t.b);
-            ms[t.cls] += m;
-            launches[t.cls] += 1.0;
-            bytes[t.cls] += t.bytes;
+            acc_ms[t.cls] += m;
+            acc_launch[t.cls] += 1.0;
+            acc_bytes[t.cls] += t.bytes_per_cell * cells;
         }
-        timed.clear();
-        ev_used = 0;
+        if (clear) {
+            v.clear();
+            ev_used = 0;
+        }
+    }
+    void collect_timing(double ms[4], double launches[4], double bytes[4])
+    {
+        harvest(timed, true);
+        for (int q = 0; q < 4; ++q) {
+            ms[q] = acc_ms[q];
+            launches[q] = acc_launch[q];
+            bytes[q] = acc_bytes[q];
+            acc_ms[q] = acc_launch[q] = acc_bytes[q] = 0.0;
+        }
+    }
+
+    // One graph per ping-pong parity for outer iterations k >= 1: the
+    // preconditioner, the conjugate-gradient step and the next limiter and
+    // residual passes.
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    std::vector<Timed> graph_timed[2];
+    std::vector<hipEvent_t> graph_events;
+    bool graphs_ok = true;
+
+    void drop_graphs()
+    {
+        for (int q = 0; q < 2; ++q) {
+            if (graph_exec[q])
+                hipGraphExecDestroy(graph_exec[q]);
+            graph_exec[q] = nullptr;
+            graph_timed[q].clear();
+        }
+        for (hipEvent_t e : graph_events)
+            hipEventDestroy(e);
+        graph_events.clear();
     }
 
     ~fld_engine_impl()
@@ -156,6 +199,7 @@ struct fld_engine_impl {
             hipStreamSynchronize(stream);
         for (hipEvent_t e : ev_pool)
             hipEventDestroy(e);
+        drop_graphs();
         for (void *p : allocs)
             hipFree(p);
         for (void *p : defl_allocs)
@@ -603,6 +647,7 @@ struct fld_engine_impl {
     fld_status finish_medium()
     {
         HK(hipStreamSynchronize(stream), "medium sync");
+        drop_graphs();
         CK(build_clusters());
         if (mg) {
             for (int l = 0; l + 1 < max_levels; ++l) {
@@ -733,6 +778,96 @@ struct fld_engine_impl {
         return FLD_OK;
     }
 
+    // Limiter and residual passes of outer iteration k (D^k, r^k, rel_k); for
+    // k past the first iteration of a call, phi^k = phi^{k-1} + theta p^{k-1}
+    // is formed on the fly.
+    void head(int k, bool first)
+    {
+        const int N = nprob;
+        hipEvent_t ta = tic();
+        if (first)
+            launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
+                           k & 1, 0, 0, 0, mixed);
+        else
+            launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
+                           (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, mixed);
+        // limiter: phi and sig_hat read, D written (FP64, plus the FP32 copy in
+        // the mixed form); with the direction update also p read, phi written
+        toc(ta, 2, 24.0 + (mixed ? 4.0 : 0.0) + (first ? 0.0 : tsz + 8.0));
+        ta = tic();
+        launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, 0, k & 1,
+                        nullptr, d_part[0], mixed);
+        // residual: phi, D, sa, j read (FP64), r written in precision T
+        toc(ta, 1, 32.0 + tsz);
+        launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_RES2, d_active);
+        launch_rel(stream, N, d_scal, d_active);
+    }
+
+    // Preconditioner and conjugate-gradient step of outer iteration k.
+    void body(int k)
+    {
+        const int N = nprob;
+        if (use_defl) {
+            launch_defl_reduce(stream, d_fines, d_ctasks, n_ctasks, d_active, k & 1, d_cpd, d_cps,
+                               mixed);
+            launch_defl_finish(stream, ncl_total, d_crange, d_cprob, d_cpd, d_cps, d_alpha,
+                               d_active);
+            launch_defl_apply(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_alpha,
+                              mixed);
+        }
+        if (mixed) {
+            coarsen_and_factor<float>();
+            vcycle<float>(use_defl ? -1 : (k & 1));
+        } else {
+            coarsen_and_factor<double>();
+            vcycle<double>(use_defl ? -1 : (k & 1));
+        }
+        launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_part[0],
+                         d_part[1], use_defl ? d_alpha : nullptr, mixed);
+        launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
+        launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
+        launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0);
+        hipEvent_t td = tic();
+        launch_npcg_dir(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
+                        (k - 1) & 1, k & 1, d_part[2], d_part[3], mixed);
+        // direction: e, p_old, r (precision T) and D, sa (FP64) read, p_new written
+        toc(td, 3, 16.0 + 4.0 * tsz);
+        launch_sum_partials(stream, N, d_fine_range, d_part[2], d_scal, S_RP, d_active);
+        launch_sum_partials(stream, N, d_fine_range, d_part[3], d_scal, S_PAP, d_active);
+        launch_npcg_theta(stream, N, d_scal, d_active);
+    }
+
+    // Capture body(k) + head(k+1) for the parity of k (k >= 1); false when
+    // the runtime refuses, after which iterations run without graphs.
+    bool capture(int k)
+    {
+        const int par = k & 1;
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return false;
+        capturing = true;
+        timed_sink = &graph_timed[par];
+        body(k);
+        head(k + 1, false);
+        capturing = false;
+        timed_sink = &timed;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(stream, &g);
+        if (e != hipSuccess || !g) {
+            (void)hipGetLastError();
+            graph_timed[par].clear();
+            return false;
+        }
+        e = hipGraphInstantiate(&graph_exec[par], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            graph_exec[par] = nullptr;
+            graph_timed[par].clear();
+            return false;
+        }
+        return true;
+    }
+
     // Multigrid solve of every problem.  start: 0 paper init / 1 given phi
     // already in phi[0] / 2 resume.
     fld_status solve_mg(int start, double *updates)
@@ -758,29 +893,13 @@ struct fld_engine_impl {
         CK(sync_active());
         const int first_k = k;
         *updates = 0.0;
+        head(k, true);
+        int replayed = -1;        // parity of the graph whose events the last sync covers
         for (;;) {
-            // D^k from phi^k; after the first iteration of this call phi^k is
-            // formed on the fly as phi^{k-1} + theta_{k-1} p^{k-1}.
-            const double cells = active_fine_cells();
-            hipEvent_t ta = tic();
-            if (k == first_k)
-                launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
-                               k & 1, k & 1, 0, 0, 0, mixed);
-            else
-                launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
-                               (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, mixed);
-            // limiter: phi and sig_hat read, D written (FP64, plus the FP32 copy in
-            // the mixed form); with the direction update also p read, phi written
-            toc(ta, 2, cells * (24.0 + (mixed ? 4.0 : 0.0) + (k == first_k ? 0.0 : tsz + 8.0)));
-            ta = tic();
-            launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, 0, k & 1,
-                            nullptr, d_part[0], mixed);
-            // residual: phi, D, sa, j read (FP64), r written in precision T
-            toc(ta, 1, cells * (32.0 + tsz));
-            launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_RES2, d_active);
-            launch_rel(stream, N, d_scal, d_active);
-            HK(hipGetLastError(), "residual launch");
+            HK(hipGetLastError(), "launch");
             CK(read_scalars(sc));
+            if (replayed >= 0)
+                harvest(graph_timed[replayed], false);
             int n_active = 0;
             for (int p = 0; p < N; ++p) {
                 if (!h_active[p])
@@ -805,40 +924,23 @@ struct fld_engine_impl {
             if (!n_active)
                 break;
             CK(sync_active());
-            if (use_defl) {
-                launch_defl_reduce(stream, d_fines, d_ctasks, n_ctasks, d_active, k & 1, d_cpd, d_cps,
-                                   mixed);
-                launch_defl_finish(stream, ncl_total, d_crange, d_cprob, d_cpd, d_cps, d_alpha,
-                                   d_active);
-                launch_defl_apply(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_alpha,
-                                  mixed);
-            }
-            if (mixed) {
-                coarsen_and_factor<float>();
-                vcycle<float>(use_defl ? -1 : (k & 1));
-            } else {
-                coarsen_and_factor<double>();
-                vcycle<double>(use_defl ? -1 : (k & 1));
-            }
             for (int p = 0; p < N; ++p)
                 if (h_active[p])
                     for (int l = 0; l + 1 < probs[p].nlev; ++l)
                         *updates += (double)probs[p].lv[l].n * (opt.nu1 + opt.nu2);
-            launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1,
-                             d_part[0], d_part[1], use_defl ? d_alpha : nullptr, mixed);
-            launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
-            launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
-            launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0);
-            const double acells = active_fine_cells();
-            hipEvent_t td = tic();
-            launch_npcg_dir(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
-                            (k - 1) & 1, k & 1, d_part[2], d_part[3], mixed);
-            // direction: e, p_old, r (precision T) and D, sa (FP64) read, p_new written
-            toc(td, 3, acells * (16.0 + 4.0 * tsz));
-            launch_sum_partials(stream, N, d_fine_range, d_part[2], d_scal, S_RP, d_active);
-            launch_sum_partials(stream, N, d_fine_range, d_part[3], d_scal, S_PAP, d_active);
-            launch_npcg_theta(stream, N, d_scal, d_active);
-            HK(hipGetLastError(), "cycle launch");
+            replayed = -1;
+            const int par = k & 1;
+            // event timing runs every kernel eagerly (events are not captured)
+            const bool use_graph = k >= 1 && opt.graph && !opt.timing && graphs_ok;
+            if (use_graph && !graph_exec[par])
+                graphs_ok = capture(k);
+            if (use_graph && graphs_ok && graph_exec[par]) {
+                HK(hipGraphLaunch(graph_exec[par], stream), "hipGraphLaunch");
+                replayed = par;
+            } else {
+                body(k);
+                head(k + 1, false);
+            }
             ++k;
         }
         k_state = k;
@@ -1047,6 +1149,7 @@ fld_status fld_default_options(fld_options *o)
     o->stream = nullptr;
     o->timing = 0;
     o->deflate_tau = 1.0;
+    o->graph = 1;
     return FLD_OK;
 }
 

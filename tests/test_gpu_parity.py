@@ -228,3 +228,21 @@ def test_mg_deflated_solve_converges_like_the_oracle():
         assert rep["status"] == F.FLD_OK
         assert rep["iterations"] <= 1.25 * ref.iterations
         assert rel_l2(phi, ref.phi) <= (1e-6 if prec == "mixed" else 1e-7)
+
+
+def test_graph_replay_is_bit_identical():
+    # outer iterations replayed from captured HIP graphs give the same bits
+    # as launching every kernel; checked over several replays of both graphs
+    st, al, Q, h = media.config("cloud256", n=32)
+    outs = []
+    for graph in (0, 1):
+        for timing in (0, 1):
+            s = gpu_solver(st.shape, h, st, al, Q, precision="mixed", tol=0.0, max_iters=9,
+                           graph=graph, timing=timing)
+            phi, rep = s.solve()
+            outs.append((phi, rep))
+            if timing:
+                assert rep["kernel_launches"][0] > 0 and rep["kernel_ms"][0] > 0
+    for phi, rep in outs[1:]:
+        np.testing.assert_array_equal(phi, outs[0][0])
+        np.testing.assert_array_equal(rep["history"], outs[0][1]["history"])
