@@ -101,8 +101,18 @@ typedef struct fld_options {
                              constant mode is removed before each V-cycle; <= 0 disables
                              (default 1)                                                  */
     int graph;            /* multigrid: replay each outer iteration from a captured HIP graph
-                             (two graphs, one per buffer parity; default 1).  Ignored when
-                             timing is set: timed kernels are launched one by one          */
+                             (two graphs, one per buffer parity; default 1).  With timing,
+                             the events become event-record nodes of the graphs           */
+    int task_cells0;      /* multigrid launch shape: cells per work-list task on the finest
+                             level (power of two in [512, 65536], default 4096)            */
+    int coarse_blocks;    /* multigrid launch shape: coarser levels use the largest power-of-
+                             two task size in [256, 4096] that still gives this many tasks
+                             per launch (64..65536, default 2048).  Neither shape changes
+                             any result bit                                                */
+    int colour_split;     /* mixed multigrid: store the finest-level FP32 fields red half /
+                             black half, so a red-black half-sweep streams only the cells it
+                             needs (used when nz % 8 == 0 and the grid coarsens; default 1).
+                             Results are bit-identical to the natural order (0)            */
 } fld_options;
 
 typedef struct fld_report {

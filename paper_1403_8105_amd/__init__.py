@@ -35,7 +35,8 @@ class fld_options(C.Structure):
                 ("nu2", C.c_int), ("max_coarsest", C.c_int), ("max_iters", C.c_int),
                 ("tol", C.c_double), ("check_every", C.c_int), ("device", C.c_int),
                 ("stream", C.c_void_p), ("timing", C.c_int), ("deflate_tau", C.c_double),
-                ("graph", C.c_int)]
+                ("graph", C.c_int), ("task_cells0", C.c_int), ("coarse_blocks", C.c_int),
+                ("colour_split", C.c_int)]
 
 
 class fld_report(C.Structure):

@@ -89,7 +89,10 @@ struct fld_engine_impl {
     DevList mid[kMaxLevels], rest[kMaxLevels], gal[kMaxLevels];
     int *d_chol_ids[kMaxLevels] = {};
     int n_chol[kMaxLevels] = {};
-    int max_coarse_n = 1;
+    int max_coarse_n = 1, max_coarse_bw = 1;
+    // kernel instance choice: kmode 0 FP64, 1 FP32 natural, 2 FP32 colour-split,
+    // 3 FP32 per problem; lsp the same for the level kernels (0 / 1 / 2)
+    int kmode = 0, lsp = 0;
     int max_levels = 0;
     double *d_part[4] = {};
     double *d_scal = nullptr;
@@ -106,6 +109,7 @@ struct fld_engine_impl {
         hipEvent_t a, b;
         int cls;
         double bytes_per_cell;
+        double cells;              // active finest cells at launch; < 0: read at harvest
     };
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -118,23 +122,61 @@ struct fld_engine_impl {
     {
         if (capturing) {
             hipEvent_t e = nullptr;
-            hipEventCreate(&e);
+            note(hipEventCreate(&e), "hipEventCreate");
             graph_events.push_back(e);
             return e;
         }
         if (ev_used == ev_pool.size()) {
             hipEvent_t e = nullptr;
-            hipEventCreate(&e);
+            note(hipEventCreate(&e), "hipEventCreate");
             ev_pool.push_back(e);
         }
         return ev_pool[ev_used++];
+    }
+    // Under capture the record becomes an event node of the graph, re-recorded
+    // on every replay.
+    void record(hipEvent_t e)
+    {
+        if (!capturing) {
+            note(hipEventRecord(e, stream), "hipEventRecord");
+            return;
+        }
+        // insert an event-record node after the captured work so far and
+        // make it the dependency of what is captured next
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        hipGraph_t g = nullptr;
+        const hipGraphNode_t *deps = nullptr;
+        size_t nd = 0;
+        hipError_t r = hipStreamGetCaptureInfo_v2(stream, &st, nullptr, &g, &deps, &nd);
+        if (r != hipSuccess || st != hipStreamCaptureStatusActive || !g) {
+            note(r != hipSuccess ? r : hipErrorIllegalState, "hipStreamGetCaptureInfo_v2");
+            return;
+        }
+        hipGraphNode_t node = nullptr;
+        r = hipGraphAddEventRecordNode(&node, g, deps, nd, e);
+        if (r != hipSuccess) {
+            note(r, "hipGraphAddEventRecordNode");
+            return;
+        }
+        note(hipStreamUpdateCaptureDependencies(stream, &node, 1, hipStreamSetCaptureDependencies),
+             "hipStreamUpdateCaptureDependencies");
+    }
+    // First failure of a call whose status is not returned at once.
+    hipError_t pending = hipSuccess;
+    const char *pending_what = "";
+    void note(hipError_t e, const char *what)
+    {
+        if (e != hipSuccess && pending == hipSuccess) {
+            pending = e;
+            pending_what = what;
+        }
     }
     hipEvent_t tic()
     {
         if (!opt.timing)
             return nullptr;
         hipEvent_t e = next_event();
-        hipEventRecord(e, stream);
+        record(e);
         return e;
     }
     void toc(hipEvent_t a, int cls, double bytes_per_cell)
@@ -142,19 +184,22 @@ struct fld_engine_impl {
         if (!opt.timing)
             return;
         hipEvent_t b = next_event();
-        hipEventRecord(b, stream);
-        timed_sink->push_back(Timed{a, b, cls, bytes_per_cell});
+        record(b);
+        // a graph's launches see the problems active when it is replayed
+        timed_sink->push_back(
+            Timed{a, b, cls, bytes_per_cell, capturing ? -1.0 : active_fine_cells()});
     }
-    // Add finished intervals to the accumulators (stream synchronised).
+    // Add finished intervals to the accumulators (stream synchronised; for
+    // a replayed graph, before the active set changes).
     void harvest(std::vector<Timed> &v, bool clear)
     {
         const double cells = active_fine_cells();
         for (const Timed &t : v) {
             float m = 0.0f;
-            hipEventElapsedTime(&m, t.a, t.b);
+            note(hipEventElapsedTime(&m, t.a, t.b), "hipEventElapsedTime");
             acc_ms[t.cls] += m;
             acc_launch[t.cls] += 1.0;
-            acc_bytes[t.cls] += t.bytes_per_cell * cells;
+            acc_bytes[t.cls] += t.bytes_per_cell * (t.cells < 0.0 ? cells : t.cells);
         }
         if (clear) {
             v.clear();
@@ -250,10 +295,19 @@ struct fld_engine_impl {
         return e == hipSuccess ? FLD_OK : hip_fail(e, "hipMemcpy tasks");
     }
 
-    static void add_tasks(std::vector<Task> &v, int grid, long long n)
+    static void add_tasks(std::vector<Task> &v, int grid, long long n, int cells = kTaskCells)
     {
-        for (long long s = 0; s < n; s += kTaskCells)
-            v.push_back(Task{grid, (int)std::min<long long>(kTaskCells, n - s), s});
+        for (long long s = 0; s < n; s += cells)
+            v.push_back(Task{grid, (int)std::min<long long>(cells, n - s), s});
+    }
+    // Largest power-of-two task size in [lo, kTaskCells] that still yields
+    // opt.coarse_blocks tasks for n cells.
+    int coarse_task(long long n, int lo) const
+    {
+        int c = kTaskCells;
+        while (c > lo && n / c < opt.coarse_blocks)
+            c >>= 1;
+        return c;
     }
 
 #define CK(x)                                    \
@@ -314,7 +368,14 @@ struct fld_engine_impl {
             f.limiter = opt.limiter;
             f.write_sighat = P.chan == 0;
             f.sig_hat = V.sig_hat;
+            // colour-split FP32 fields: the split smoother needs 8-cell z runs,
+            // and the finest level must be smoothed (not the coarsest)
+            const bool coarsens = V.nx % 2 == 0 && V.ny % 2 == 0 && V.nz % 2 == 0 &&
+                                  V.nx / 2 >= 4 && V.ny / 2 >= 4 && V.nz / 2 >= 4;
+            f.split = mixed && mg && opt.colour_split && V.nz % 8 == 0 && coarsens;
             const size_t N8 = sizeof(double) * V.n, NT = tsz * V.n;
+            // split fields hold whole 64-cell blocks
+            const size_t NS = f.split ? tsz * (size_t)((V.n + 63) / 64 * 64) : NT;
             CK(dalloc(&f.sa64, N8));
             CK(dalloc(&f.j, N8));
             CK(dalloc(&f.phi[0], N8));
@@ -322,17 +383,17 @@ struct fld_engine_impl {
             CK(dalloc(&f.D64, N8));
             if (!mg)
                 CK(dalloc(&f.Dtmp, N8));
-            CK(dalloc(&f.b0[0], NT));
-            CK(dalloc(&f.b0[1], NT));
+            CK(dalloc(&f.b0[0], NS));
+            CK(dalloc(&f.b0[1], NS));
             if (mg) {
-                CK(dalloc(&f.e0, NT));
+                CK(dalloc(&f.e0, NS));
                 CK(dalloc(&f.p[0], NT));
                 CK(dalloc(&f.p[1], NT));
                 if (opt.deflate_tau > 0.0)
-                    CK(dalloc(&f.b1, NT));
+                    CK(dalloc(&f.b1, NS));
                 if (mixed) {
-                    CK(dalloc(&f.D0, NT));
-                    CK(dalloc(&f.sa0, NT));
+                    CK(dalloc(&f.D0, NS));
+                    CK(dalloc(&f.sa0, NS));
                 } else {
                     f.D0 = f.D64;
                     f.sa0 = f.sa64;
@@ -346,6 +407,13 @@ struct fld_engine_impl {
             add_tasks(ft, p, V.n);
             fine_range[p + 1] = (int)ft.size();
             hf[p] = f;
+        }
+        {
+            int ns = 0;
+            for (const Prob &P : probs)
+                ns += P.fine.split ? 1 : 0;
+            lsp = ns == 0 ? 0 : ns == nprob ? 1 : 2;
+            kmode = !mixed ? 0 : lsp + 1;
         }
         CK(upload_list(ft, fine_tasks));
         CK(dalloc(&d_fine_range, sizeof(int) * (nprob + 1)));
@@ -402,6 +470,7 @@ struct fld_engine_impl {
                     const long long W = (long long)L.ny * L.nz + 1;
                     CK(dalloc(&L.band, sizeof(double) * L.n * W));
                     max_coarse_n = std::max<int>(max_coarse_n, (int)L.n);
+                    max_coarse_bw = std::max<int>(max_coarse_bw, L.ny * L.nz);
                 }
             }
             P.gid0 = (int)grids[0].size();
@@ -412,6 +481,7 @@ struct fld_engine_impl {
                 g.h2 = L.h * L.h;
                 g.dghost = P.fine.dghost;
                 g.fine = l == 0;
+                g.split = l == 0 && P.fine.split;
                 g.mirror = P.fine.mirror;
                 g.finer = l > 0 ? P.gid0 + l - 1 : -1;
                 g.coarser = l + 1 < P.nlev ? P.gid0 + l + 1 : -1;
@@ -441,13 +511,25 @@ struct fld_engine_impl {
         for (int l = 0; l < max_levels; ++l) {
             std::vector<Task> m, r, g;
             std::vector<int> ch;
+            // launch shape: task sizes from the cells all problems hold at this level
+            long long nm = 0, nr = 0, ng = 0;
+            for (const Prob &P : probs)
+                if (l < P.nlev - 1) {
+                    const Level &C = P.lv[l + 1];
+                    nm += P.lv[l].n;
+                    nr += C.n;
+                    ng += (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
+                }
+            const int tm = l == 0 ? opt.task_cells0 : coarse_task(nm, 512);
+            const int tr = coarse_task(nr, 256), tg = coarse_task(ng, 256);
             for (int p = 0; p < nprob; ++p) {
                 const Prob &P = probs[p];
                 if (l < P.nlev - 1) {
-                    add_tasks(m, P.gid0 + l, P.lv[l].n);
-                    add_tasks(r, P.gid0 + l + 1, P.lv[l + 1].n);
+                    add_tasks(m, P.gid0 + l, P.lv[l].n, tm);
+                    add_tasks(r, P.gid0 + l + 1, P.lv[l + 1].n, tr);
                     const Level &C = P.lv[l + 1];
-                    add_tasks(g, P.gid0 + l + 1, (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1));
+                    add_tasks(g, P.gid0 + l + 1, (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1),
+                              tg);
                 } else if (l == P.nlev - 1) {
                     ch.push_back(P.gid0 + l);
                 }
@@ -694,25 +776,24 @@ struct fld_engine_impl {
     // ---- multigrid cycle --------------------------------------------------
 
     template <typename T>
-    void coarsen_and_factor()
+    void coarsen()
     {
         Grid *G = d_grids[0];
         for (int l = 0; l + 1 < max_levels; ++l)
             if (gal[l].n)
-                launch_galerkin<T>(stream, G, gal[l].d, gal[l].n, d_active);
-        for (int l = 0; l < max_levels; ++l)
-            launch_chol_factor<T>(stream, G, d_chol_ids[l], n_chol[l], d_active, d_fail);
+                launch_galerkin<T>(stream, G, gal[l].d, gal[l].n, d_active, lsp);
     }
 
-    // One finest-level half-sweep moves (per cell) half of e read, all of D,
-    // half of b and sa, half of e written: 6 values of precision T.
+    // One finest-level half-sweep must move, per cell of the grid, the other
+    // colour's e (half), all of D, this colour's b and sa (half each) and its
+    // new e (half): 3 values of precision T.
     template <typename T>
     void smooth(Grid *G, int l, int colour)
     {
         hipEvent_t a = l == 0 ? tic() : nullptr;
-        launch_smooth<T>(stream, G, mid[l].d, mid[l].n, d_active, colour, opt.omega_s);
+        launch_smooth<T>(stream, G, mid[l].d, mid[l].n, d_active, colour, opt.omega_s, l == 0);
         if (l == 0)
-            toc(a, 0, 3.0 * sizeof(T) * active_fine_cells());
+            toc(a, 0, 3.0 * sizeof(T));
     }
 
     double active_fine_cells() const
@@ -736,14 +817,15 @@ struct fld_engine_impl {
                     smooth<T>(G, l, 0);
                     smooth<T>(G, l, 1);
                 }
-                launch_restrict<T>(stream, G, rest[l].d, rest[l].n, d_active);
+                launch_restrict<T>(stream, G, rest[l].d, rest[l].n, d_active, lsp);
             }
-            launch_chol_solve<T>(stream, G, d_chol_ids[l], n_chol[l], d_active, max_coarse_n);
+            launch_coarse_solve<T>(stream, G, d_chol_ids[l], n_chol[l], d_active, d_fail,
+                                   max_coarse_n, max_coarse_bw);
         }
         for (int l = max_levels - 2; l >= 0; --l) {
             if (!mid[l].n)
                 continue;
-            launch_prolong<T>(stream, G, mid[l].d, mid[l].n, d_active);
+            launch_prolong<T>(stream, G, mid[l].d, mid[l].n, d_active, lsp);
             for (int s = 0; s < opt.nu2; ++s) {
                 smooth<T>(G, l, 1);
                 smooth<T>(G, l, 0);
@@ -787,16 +869,16 @@ struct fld_engine_impl {
         hipEvent_t ta = tic();
         if (first)
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
-                           k & 1, 0, 0, 0, mixed);
+                           k & 1, 0, 0, 0, kmode);
         else
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
-                           (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, mixed);
+                           (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, kmode);
         // limiter: phi and sig_hat read, D written (FP64, plus the FP32 copy in
         // the mixed form); with the direction update also p read, phi written
         toc(ta, 2, 24.0 + (mixed ? 4.0 : 0.0) + (first ? 0.0 : tsz + 8.0));
         ta = tic();
         launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, 0, k & 1,
-                        nullptr, d_part[0], mixed);
+                        nullptr, d_part[0], kmode);
         // residual: phi, D, sa, j read (FP64), r written in precision T
         toc(ta, 1, 32.0 + tsz);
         launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_RES2, d_active);
@@ -809,27 +891,27 @@ struct fld_engine_impl {
         const int N = nprob;
         if (use_defl) {
             launch_defl_reduce(stream, d_fines, d_ctasks, n_ctasks, d_active, k & 1, d_cpd, d_cps,
-                               mixed);
+                               kmode);
             launch_defl_finish(stream, ncl_total, d_crange, d_cprob, d_cpd, d_cps, d_alpha,
                                d_active);
             launch_defl_apply(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_alpha,
-                              mixed);
+                              kmode);
         }
         if (mixed) {
-            coarsen_and_factor<float>();
+            coarsen<float>();
             vcycle<float>(use_defl ? -1 : (k & 1));
         } else {
-            coarsen_and_factor<double>();
+            coarsen<double>();
             vcycle<double>(use_defl ? -1 : (k & 1));
         }
         launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_part[0],
-                         d_part[1], use_defl ? d_alpha : nullptr, mixed);
+                         d_part[1], use_defl ? d_alpha : nullptr, kmode);
         launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
         launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
         launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0);
         hipEvent_t td = tic();
         launch_npcg_dir(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
-                        (k - 1) & 1, k & 1, d_part[2], d_part[3], mixed);
+                        (k - 1) & 1, k & 1, d_part[2], d_part[3], kmode);
         // direction: e, p_old, r (precision T) and D, sa (FP64) read, p_new written
         toc(td, 3, 16.0 + 4.0 * tsz);
         launch_sum_partials(stream, N, d_fine_range, d_part[2], d_scal, S_RP, d_active);
@@ -842,8 +924,10 @@ struct fld_engine_impl {
     bool capture(int k)
     {
         const int par = k & 1;
-        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
             return false;
+        }
         capturing = true;
         timed_sink = &graph_timed[par];
         body(k);
@@ -896,6 +980,12 @@ struct fld_engine_impl {
         head(k, true);
         int replayed = -1;        // parity of the graph whose events the last sync covers
         for (;;) {
+            if (pending != hipSuccess) {
+                const hipError_t e = pending;
+                pending = hipSuccess;
+                (void)hipGetLastError();
+                return hip_fail(e, pending_what);
+            }
             HK(hipGetLastError(), "launch");
             CK(read_scalars(sc));
             if (replayed >= 0)
@@ -930,8 +1020,7 @@ struct fld_engine_impl {
                         *updates += (double)probs[p].lv[l].n * (opt.nu1 + opt.nu2);
             replayed = -1;
             const int par = k & 1;
-            // event timing runs every kernel eagerly (events are not captured)
-            const bool use_graph = k >= 1 && opt.graph && !opt.timing && graphs_ok;
+            const bool use_graph = k >= 1 && opt.graph && graphs_ok;
             if (use_graph && !graph_exec[par])
                 graphs_ok = capture(k);
             if (use_graph && graphs_ok && graph_exec[par]) {
@@ -952,10 +1041,11 @@ struct fld_engine_impl {
         // phi[0] already holds the start; zero the direction/rhs ping-pongs.
         for (Prob &P : probs) {
             const size_t NT = tsz * P.fine.n;
+            const size_t NS = P.fine.split ? tsz * (size_t)((P.fine.n + 63) / 64 * 64) : NT;
             hipMemsetAsync(P.fine.p[0], 0, NT, stream);
             hipMemsetAsync(P.fine.p[1], 0, NT, stream);
-            hipMemsetAsync(P.fine.b0[0], 0, NT, stream);
-            hipMemsetAsync(P.fine.b0[1], 0, NT, stream);
+            hipMemsetAsync(P.fine.b0[0], 0, NS, stream);
+            hipMemsetAsync(P.fine.b0[1], 0, NS, stream);
         }
     }
 
@@ -1067,6 +1157,9 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->check_every < 1) { err = "check_every must be >= 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->device < 0) { err = "device must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!std::isfinite(o->deflate_tau)) { err = "deflate_tau must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->task_cells0 < 512 || o->task_cells0 > 65536 || (o->task_cells0 & (o->task_cells0 - 1))) { err = "task_cells0 must be a power of two in [512,65536]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->coarse_blocks < 64 || o->coarse_blocks > 65536) { err = "coarse_blocks must lie in [64,65536]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->colour_split != 0 && o->colour_split != 1) { err = "colour_split must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1150,6 +1243,9 @@ fld_status fld_default_options(fld_options *o)
     o->timing = 0;
     o->deflate_tau = 1.0;
     o->graph = 1;
+    o->task_cells0 = 4096;
+    o->coarse_blocks = 2048;
+    o->colour_split = 1;
     return FLD_OK;
 }
 

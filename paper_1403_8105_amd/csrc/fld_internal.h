@@ -25,6 +25,8 @@ struct Grid {
     int mirror;      // finest level: ghost D = D of the voxel inside
     int finer;       // index of the next finer grid in the same table (-1: none)
     int coarser;     // index of the next coarser grid (-1: none)
+    int split;       // e, b, sa, D stored colour by colour (see Fine::split)
+    int pad;
     void *e, *b, *sa, *D, *f;
     double *band;    // coarsest level: banded Cholesky factor of h^2 A, n*(ny*nz+1)
 };
@@ -41,7 +43,10 @@ struct Fine {
     int nx, ny, nz, prob;
     long long n;
     double h, h2, dghost, eps, phi_b, larsen_n;
-    int mirror, limiter, write_sighat, pad;
+    int mirror, limiter, write_sighat;
+    int split;           // precision-T fields e0, b0, b1, D0, sa0 stored colour by colour in
+                         // blocks of 64 cells: cell c of colour q = (i+j+k)&1 at
+                         // (c>>6)*64 + q*32 + ((c>>1)&31); nz % 8 == 0
     double *sig_hat, *sa64, *j;
     double *phi[2];      // fluence ping-pong: phi^k lives in phi[k & 1]
     double *D64;         // limiter output (multigrid) / Algorithm 1 state D
@@ -83,6 +88,10 @@ enum Limiter { L_CDA = 0, L_LP = 1, L_SUM = 2, L_MAX = 3, L_KERSHAW = 4, L_LARSE
 // Algorithm 1 set-up for one problem: sig_hat = max(sigma_t, sigma_eps)
 // (written when f.write_sighat), sa = (1 - albedo) sig_hat, j = Q, partial
 // sums of Q^2 per task.
+// Fine-level launchers take `mixed` as a precision/layout mode: 0 FP64,
+// 1 FP32 natural order, 2 FP32 colour-split, 3 FP32 decided per problem.
+// Level launchers take sp: 0 natural, 1 colour-split finest level, 2 per
+// problem.
 void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
                   const double *sigma_t, const double *albedo, const double *Q,
                   double sigma_eps, double *partials, int mixed);
@@ -127,25 +136,22 @@ void launch_zero(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks
                  const int *active);
 template <typename T>
 void launch_smooth(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                   const int *active, int colour, double omega);
+                   const int *active, int colour, double omega, bool finest);
 template <typename T>
 void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                     const int *active);
+                     const int *active, int sp);
 template <typename T>
 void launch_prolong(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                    const int *active);
+                    const int *active, int sp);
 template <typename T>
 void launch_galerkin(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                     const int *active);
+                     const int *active, int sp);
 template <typename T>
 void launch_mean8_sa(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks);
 // Coarsest level: one block per listed grid.  fail[prob] is set to 1 when a
 // pivot is not positive.
 template <typename T>
-void launch_chol_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
-                        const int *active, int *fail);
-template <typename T>
-void launch_chol_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
-                       const int *active, int max_n);
+void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
+                         const int *active, int *fail, int max_n, int max_bw);
 
 }  // namespace fld

@@ -94,6 +94,81 @@ __device__ inline void st4(double *p, const double v[4])
     *reinterpret_cast<double2 *>(p + 2) = make_double2(v[2], v[3]);
 }
 
+// ---------------------------------------------------------------------------
+// Colour-split storage (finest level of the mixed form, nz % 8 == 0).  The
+// cells pair up along z, c and c+1 (c even) sharing the compact index
+// m = c >> 1; one of the two is red ((i+j+k) even), the other black.  Blocks
+// of 32 compact indices are stored as 32 red values then 32 black values
+// (2 x 128 bytes in FP32), so cell c of colour q lives at
+// (c >> 6) * 64 + q * 32 + ((c >> 1) & 31).  A red-black half-sweep then
+// streams whole cache lines of only the colours it needs, while a kernel
+// walking cells in natural order still touches one contiguous window.  A
+// natural quad c0..c0+3 (c0 % 4 == 0) is two pairs: two 2-value runs.
+// Arrays hold n rounded up to 64 values.
+// ---------------------------------------------------------------------------
+
+__device__ inline long long sidx(long long c, int q)
+{
+    return ((c >> 6) << 6) + (q << 5) + ((c >> 1) & 31);
+}
+// Whether a kernel instance sees split storage: SP = 0 natural, 1 split,
+// 2 decided per problem at run time (batches mixing both).
+template <int SP>
+__device__ inline bool layout_split(int flag)
+{
+    return SP == 2 ? flag != 0 : SP == 1;
+}
+// The same for a multigrid level: only finest levels are ever split.
+template <int SP>
+__device__ inline bool grid_split(const Grid &g)
+{
+    return SP == 2 ? g.split != 0 : SP == 1 && g.fine;
+}
+// Storage place of compact index m (= c >> 1) of colour q.
+__device__ inline long long cpos(long long m, int q)
+{
+    return ((m >> 5) << 6) + (q << 5) + (m & 31);
+}
+template <typename V> struct Pair;
+template <> struct Pair<float> { using type = float2; };
+template <> struct Pair<double> { using type = double2; };
+// Quad of natural cells c0..c0+3 whose first cell has colour q0.
+template <typename V>
+__device__ inline void ld4s(const V *base, long long c0, int q0, V v[4])
+{
+    using P2 = typename Pair<V>::type;
+    const P2 a = *reinterpret_cast<const P2 *>(base + sidx(c0, q0));
+    const P2 b = *reinterpret_cast<const P2 *>(base + sidx(c0, q0 ^ 1));
+    v[0] = a.x; v[1] = b.x; v[2] = a.y; v[3] = b.y;
+}
+template <typename V>
+__device__ inline void st4s(V *base, long long c0, int q0, const V v[4])
+{
+    using P2 = typename Pair<V>::type;
+    *reinterpret_cast<P2 *>(base + sidx(c0, q0)) = P2{v[0], v[2]};
+    *reinterpret_cast<P2 *>(base + sidx(c0, q0 ^ 1)) = P2{v[1], v[3]};
+}
+// Quad / single loads of a split or natural array inside a gather() around
+// the quad at c0 (colour q0): its x/y neighbour quads and the cell before it
+// along z have the other colour, the cell after it the same.
+template <typename V>
+struct QuadSrc {
+    const V *base;
+    long long c0;
+    int q0, split;
+    __device__ void quad(long long x, V v[4]) const
+    {
+        if (split)
+            ld4s(base, x, x == c0 ? q0 : q0 ^ 1, v);
+        else
+            ld4(base + x, v);
+    }
+    __device__ V one(long long x) const
+    {
+        return split ? base[sidx(x, x < c0 ? q0 ^ 1 : q0)] : base[x];
+    }
+};
+
 // The 7-point neighbourhood of a quad: centre values, the four in-plane /
 // out-of-plane neighbour quads, and the single cells before and after it
 // along z.  `G` is the value used for ghost cells (callers fill ghost quads
@@ -196,6 +271,7 @@ k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const doub
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         double acc = 0.0;
+        const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             const double sh = fmax(sigma_t[c], sigma_eps);
@@ -203,8 +279,15 @@ k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const doub
                 f.sig_hat[c] = sh;
             const double sa = (1.0 - albedo[c]) * sh;
             f.sa64[c] = sa;
-            if (sa32)
-                sa32[c] = (float)sa;
+            if (sa32) {
+                long long o = c;
+                if (f.split) {
+                    int i, j, k;
+                    dec(c, i, j, k);
+                    o = sidx(c, (i + j + k) & 1);
+                }
+                sa32[o] = (float)sa;
+            }
             const double jq = Q[c];
             f.j[c] = jq;
             acc += jq * jq;
@@ -223,6 +306,7 @@ k_init_phi(const Fine *fines, const Task *tasks, int ntasks, const double *scal,
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
         const double v = f.eps * scal[f.prob * S_COUNT + S_JBAR] * f.h;
+        const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             f.phi[0][c] = v;
@@ -231,8 +315,14 @@ k_init_phi(const Fine *fines, const Task *tasks, int ntasks, const double *scal,
             if (zero_dirs) {
                 ((T *)f.p[0])[c] = (T)0;
                 ((T *)f.p[1])[c] = (T)0;
-                ((T *)f.b0[0])[c] = (T)0;
-                ((T *)f.b0[1])[c] = (T)0;
+                long long o = c;
+                if (f.split) {
+                    int i, j, k;
+                    dec(c, i, j, k);
+                    o = sidx(c, (i + j + k) & 1);
+                }
+                ((T *)f.b0[0])[o] = (T)0;
+                ((T *)f.b0[1])[o] = (T)0;
             }
         }
     }
@@ -241,7 +331,7 @@ k_init_phi(const Fine *fines, const Task *tasks, int ntasks, const double *scal,
 // Limiter pass: (optionally) phi <- phi + theta*p, then for every voxel the
 // central-difference gradient, the guarded Knudsen number and
 // D = F(R)/sig_hat (Sec. 5: grad_approx, knudsen_numerical, D_update).
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, const double *scal,
           int src, int dst, int use_dir, int dir_idx, int to_tmp)
@@ -249,6 +339,7 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob])
             continue;
         const double *__restrict__ phi = f.phi[src];
@@ -301,8 +392,12 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
                     D32q[m] = (float)Dq[m];
                 }
                 st4(Dout + c0, Dq);
-                if (!to_tmp && sizeof(T) == 4)
-                    st4(D32 + c0, D32q);
+                if (!to_tmp && sizeof(T) == 4) {
+                    if (sp)
+                        st4s(D32, c0, (i + j) & 1, D32q);
+                    else
+                        st4(D32 + c0, D32q);
+                }
             }
             continue;
         }
@@ -331,7 +426,7 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
             const double D = limiter(f.limiter, R, f.larsen_n) / sh;
             Dout[c] = D;
             if (!to_tmp && sizeof(T) == 4)
-                D32[c] = (float)D;
+                D32[sp ? sidx(c, (i + j + k) & 1) : c] = (float)D;
             if (use_dir && dst != src)
                 phi_out[c] = pc;
         }
@@ -342,7 +437,7 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
 // r = (num - phi*den)/h^2, num = j h^2 + sum_s D_ps phi_s,
 // den = sa h^2 + sum_s D_ps, D_ps = (D_p + D_s)/2.  Writes r in precision T
 // as the V-cycle right-hand side and per-task partial sums of r^2.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, int src,
            int use_tmp, int b0_idx, double *r_out, double *partials)
@@ -350,6 +445,7 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob]) {
             if (threadIdx.x == 0)
                 partials[t] = 0.0;
@@ -395,7 +491,10 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
                     bq[m] = (T)rq[m];
                     acc += rq[m] * rq[m];
                 }
-                st4(b0 + c0, bq);
+                if (sp)
+                    st4s(b0, c0, (i + j) & 1, bq);
+                else
+                    st4(b0 + c0, bq);
                 if (r_out)
                     st4(r_out + c0, rq);
             }
@@ -429,7 +528,7 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
             num = num + F * (k < f.nz - 1 ? phi[c + 1] : f.phi_b);
             den = den + F;
             const double r = (num - phi[c] * den) / f.h2;
-            b0[c] = (T)r;
+            b0[sp ? sidx(c, (i + j + k) & 1) : c] = (T)r;
             if (r_out)
                 r_out[c] = r;
             acc += r * r;
@@ -442,7 +541,7 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
 
 // gamma = b0 . e and sigma = e . b0_prev (conjugate-gradient coefficients).
 // With deflation the cluster correction is first added: e0 += alpha[label].
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
             double *pg, double *ps, const double *alpha)
@@ -450,19 +549,31 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob])
             continue;
         const T *b = (const T *)f.b0[b0_idx];
         const T *bp = (const T *)f.b0[b0_idx ^ 1];
         T *e = (T *)f.e0;
         double g = 0.0, sg = 0.0;
+        const Dec dec(f.ny, f.nz);
         if ((f.nz & 3) == 0) {
             for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
                 const long long c0 = tk.start + 4 * (long long)q;
                 T eq[4], bq[4], bpq[4];
-                ld4(e + c0, eq);
-                ld4(b + c0, bq);
-                ld4(bp + c0, bpq);
+                int q0 = 0;
+                if (sp) {
+                    int i, j, k0;
+                    dec(c0, i, j, k0);
+                    q0 = (i + j) & 1;
+                    ld4s(e, c0, q0, eq);
+                    ld4s(b, c0, q0, bq);
+                    ld4s(bp, c0, q0, bpq);
+                } else {
+                    ld4(e + c0, eq);
+                    ld4(b + c0, bq);
+                    ld4(bp + c0, bpq);
+                }
                 if (alpha) {
                     int lq[4];
                     ld4(f.label + c0, lq);
@@ -470,7 +581,10 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
                         for (int m = 0; m < 4; ++m)
                             if (lq[m] >= 0)
                                 eq[m] = (T)(alpha[f.cbase + lq[m]] + (double)eq[m]);
-                        st4(e + c0, eq);
+                        if (sp)
+                            st4s(e, c0, q0, eq);
+                        else
+                            st4(e + c0, eq);
                     }
                 }
                 for (int m = 0; m < 4; ++m) {
@@ -482,17 +596,23 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
         } else
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
-            double ev = (double)e[c];
+            long long o = c;
+            if (sp) {
+                int i, j, k;
+                dec(c, i, j, k);
+                o = sidx(c, (i + j + k) & 1);
+            }
+            double ev = (double)e[o];
             if (alpha) {
                 const int l = f.label[c];
                 if (l >= 0) {
                     ev = alpha[f.cbase + l] + ev;
-                    e[c] = (T)ev;
-                    ev = (double)e[c];
+                    e[o] = (T)ev;
+                    ev = (double)e[o];
                 }
             }
-            g += (double)b[c] * ev;
-            sg += ev * (double)bp[c];
+            g += (double)b[o] * ev;
+            sg += ev * (double)bp[o];
         }
         g = block_sum(g);
         sg = block_sum(sg);
@@ -506,7 +626,7 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
 // p_new = e + beta p_old (stored in precision T) and the partial sums of
 // r . p_new and p_new . A(D) p_new with the FP64 finest operator
 // (A x)_c = (x_c den - sum_s D_ps x_s)/h^2, zero ghosts.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, const double *scal,
            int b0_idx, int pin, int pout, double *prp, double *ppap)
@@ -514,6 +634,7 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob])
             continue;
         const T *__restrict__ e = (const T *)f.e0;
@@ -527,27 +648,35 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
         double arp = 0.0, apap = 0.0;
         const Dec dec(f.ny, f.nz);
         if ((f.nz & 3) == 0) {
+            QuadSrc<T> Es{e, 0, 0, sp};
             auto P4 = [&](long long x, double v[4]) {
                 T ev[4], pv[4];
-                ld4(e + x, ev);
+                Es.quad(x, ev);
                 ld4(po + x, pv);
                 for (int m = 0; m < 4; ++m)
                     v[m] = (double)(T)((double)ev[m] + beta * (double)pv[m]);
             };
-            auto P1 = [&](long long x) { return (double)(T)((double)e[x] + beta * (double)po[x]); };
+            auto P1 = [&](long long x) {
+                return (double)(T)((double)Es.one(x) + beta * (double)po[x]);
+            };
             auto D4 = [&](long long x, double v[4]) { ld4(D + x, v); };
             auto D1 = [&](long long x) { return D[x]; };
             for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
                 const long long c0 = tk.start + 4 * (long long)q;
                 int i, j, k0;
                 dec(c0, i, j, k0);
+                Es.c0 = c0;
+                Es.q0 = (i + j) & 1;
                 Hood<double> P, Dh;
                 gather(P, P4, P1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, 0.0);
                 gather(Dh, D4, D1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, f.dghost);
                 double saq[4];
                 T bq[4], pq[4];
                 ld4(sa + c0, saq);
-                ld4(b + c0, bq);
+                if (sp)
+                    ld4s(b, c0, Es.q0, bq);
+                else
+                    ld4(b + c0, bq);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     double F[6];
@@ -574,7 +703,11 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
             const long long c = tk.start + q;
             int i, j, k;
             dec(c, i, j, k);
-            auto pv = [&](long long x) { return (double)(T)((double)e[x] + beta * (double)po[x]); };
+            const int qc = (i + j + k) & 1;
+            auto eat = [&](long long x) {
+                return sp ? e[sidx(x, x == c ? qc : qc ^ 1)] : e[x];
+            };
+            auto pv = [&](long long x) { return (double)(T)((double)eat(x) + beta * (double)po[x]); };
             const double Dc = D[c];
             const double gD = f.mirror ? Dc : f.dghost;
             const double pc = pv(c);
@@ -601,7 +734,7 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
             den = den + F;
             const double Ap = (pc * den - nb) / f.h2;
             pn[c] = (T)pc;
-            arp += (double)b[c] * pc;
+            arp += (double)b[sp ? sidx(c, qc) : c] * pc;
             apap += pc * Ap;
         }
         arp = block_sum(arp);
@@ -616,7 +749,7 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
 // Cluster deflation, reduction pass: for the voxels of each task (all in one
 // cluster) the contributions to the cluster Galerkin diagonal
 // d_c = sum sa + sum_{faces leaving c} F/h^2 and to s_c = sum b0.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, int b0_idx,
               double *pd, double *ps)
@@ -624,6 +757,7 @@ k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, in
     for (int t = blockIdx.x; t < nct; t += gridDim.x) {
         const CTask tk = ct[t];
         const Fine &f = fines[tk.prob];
+        const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob]) {
             if (threadIdx.x == 0) {
                 pd[t] = 0.0;
@@ -636,27 +770,37 @@ k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, in
         const T *b = (const T *)f.b0[b0_idx];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         const double gD0 = (double)(T)f.dghost;
+        const Dec dec(f.ny, f.nz);
         double ad = 0.0, as = 0.0;
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = f.ccells[tk.start + q];
             const int mask = f.cmask[tk.start + q];
-            double v = (double)sa[c];
+            int qc = 0;
+            if (sp) {
+                int i, j, k;
+                dec(c, i, j, k);
+                qc = (i + j + k) & 1;
+            }
+            // own cell / a face neighbour (the other colour)
+            auto at = [&](long long x, int qq) { return sp ? sidx(x, qq) : x; };
+            double v = (double)sa[at(c, qc)];
             if (mask) {
                 // faces leaving the cluster: bit s set for neighbour s
                 // (x-, x+, y-, y+, z-, z+); bit s+6 set when it is a ghost
-                const double Dc = (double)D[c];
+                const double Dc = (double)D[at(c, qc)];
                 const double gD = f.mirror ? Dc : gD0;
                 const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
 #pragma unroll
                 for (int d = 0; d < 6; ++d)
                     if (mask & (1 << d)) {
                         const bool ghost = (mask >> (d + 6)) & 1;
-                        const double F = 0.5 * (Dc + (ghost ? gD : (double)D[c + off[d]]));
+                        const double F =
+                            0.5 * (Dc + (ghost ? gD : (double)D[at(c + off[d], qc ^ 1)]));
                         v = v + F / f.h2;
                     }
             }
             ad += v;
-            as += (double)b[c];
+            as += (double)b[at(c, qc)];
         }
         ad = block_sum(ad);
         as = block_sum(as);
@@ -689,7 +833,7 @@ k_defl_finish(const int *crange, const int *cprob, const double *pd, const doubl
 // Deflated right-hand side b1 = b0 - A e1 with e1 = alpha[label] (zero
 // outside clusters); A is the finest operator in the coefficients of the
 // V-cycle, (A x)_c = (x_c den - sum_s F_s x_s)/h^2.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
              const double *alpha)
@@ -697,6 +841,7 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob])
             continue;
         const T *__restrict__ D = (const T *)f.D0;
@@ -709,6 +854,7 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
         const double gD0 = (double)(T)f.dghost;
         const Dec dec(f.ny, f.nz);
         if ((f.nz & 3) == 0) {
+            QuadSrc<T> Ds{D, 0, 0, sp};
             auto A4 = [&](long long x, double v[4]) {
                 int l[4];
                 ld4(lab + x, l);
@@ -721,15 +867,18 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
             };
             auto D4 = [&](long long x, double v[4]) {
                 T t[4];
-                ld4(D + x, t);
+                Ds.quad(x, t);
                 for (int m = 0; m < 4; ++m)
                     v[m] = (double)t[m];
             };
-            auto D1 = [&](long long x) { return (double)D[x]; };
+            auto D1 = [&](long long x) { return (double)Ds.one(x); };
             for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
                 const long long c0 = tk.start + 4 * (long long)q;
                 int i, j, k0;
                 dec(c0, i, j, k0);
+                const int q0 = (i + j) & 1;
+                Ds.c0 = c0;
+                Ds.q0 = q0;
                 Hood<double> Eh;
                 gather(Eh, A4, A1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, 0.0);
                 bool any = Eh.zl != 0.0 || Eh.zr != 0.0;
@@ -737,15 +886,24 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
                     any = any || Eh.c[m] != 0.0 || Eh.xm[m] != 0.0 || Eh.xp[m] != 0.0 ||
                           Eh.ym[m] != 0.0 || Eh.yp[m] != 0.0;
                 T bq[4];
-                ld4(b + c0, bq);
+                if (sp)
+                    ld4s(b, c0, q0, bq);
+                else
+                    ld4(b + c0, bq);
                 if (!any) {
-                    st4(b1 + c0, bq);
+                    if (sp)
+                        st4s(b1, c0, q0, bq);
+                    else
+                        st4(b1 + c0, bq);
                     continue;
                 }
                 Hood<double> Dh;
                 gather(Dh, D4, D1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, gD0);
                 T saq[4], out[4];
-                ld4(sa + c0, saq);
+                if (sp)
+                    ld4s(sa, c0, q0, saq);
+                else
+                    ld4(sa + c0, saq);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     double Fc[6];
@@ -761,7 +919,10 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
                     const double Ae = (Eh.c[m] * den - nb) / f.h2;
                     out[m] = (T)((double)bq[m] - Ae);
                 }
-                st4(b1 + c0, out);
+                if (sp)
+                    st4s(b1, c0, q0, out);
+                else
+                    st4(b1 + c0, out);
             }
             continue;
         }
@@ -779,36 +940,39 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
             const double exm = ev(i > 0, c - sx), exp_ = ev(i < f.nx - 1, c + sx);
             const double eym = ev(j > 0, c - sy), eyp = ev(j < f.ny - 1, c + sy);
             const double ezm = ev(k > 0, c - 1), ezp = ev(k < f.nz - 1, c + 1);
+            const int qc = (i + j + k) & 1;
+            const long long oc = sp ? sidx(c, qc) : c;
+            auto Dn = [&](long long x) { return (double)D[sp ? sidx(x, qc ^ 1) : x]; };
             if (e_c == 0.0 && exm == 0.0 && exp_ == 0.0 && eym == 0.0 && eyp == 0.0 &&
                 ezm == 0.0 && ezp == 0.0) {
-                b1[c] = b[c];
+                b1[oc] = b[oc];
                 continue;
             }
-            const double Dc = (double)D[c];
+            const double Dc = (double)D[oc];
             const double gD = f.mirror ? Dc : gD0;
             double nb = 0.0;
-            double den = (double)sa[c] * f.h2;
+            double den = (double)sa[oc] * f.h2;
             double F;
-            F = 0.5 * (Dc + (i > 0 ? (double)D[c - sx] : gD));
+            F = 0.5 * (Dc + (i > 0 ? Dn(c - sx) : gD));
             nb = nb + F * exm;
             den = den + F;
-            F = 0.5 * (Dc + (i < f.nx - 1 ? (double)D[c + sx] : gD));
+            F = 0.5 * (Dc + (i < f.nx - 1 ? Dn(c + sx) : gD));
             nb = nb + F * exp_;
             den = den + F;
-            F = 0.5 * (Dc + (j > 0 ? (double)D[c - sy] : gD));
+            F = 0.5 * (Dc + (j > 0 ? Dn(c - sy) : gD));
             nb = nb + F * eym;
             den = den + F;
-            F = 0.5 * (Dc + (j < f.ny - 1 ? (double)D[c + sy] : gD));
+            F = 0.5 * (Dc + (j < f.ny - 1 ? Dn(c + sy) : gD));
             nb = nb + F * eyp;
             den = den + F;
-            F = 0.5 * (Dc + (k > 0 ? (double)D[c - 1] : gD));
+            F = 0.5 * (Dc + (k > 0 ? Dn(c - 1) : gD));
             nb = nb + F * ezm;
             den = den + F;
-            F = 0.5 * (Dc + (k < f.nz - 1 ? (double)D[c + 1] : gD));
+            F = 0.5 * (Dc + (k < f.nz - 1 ? Dn(c + 1) : gD));
             nb = nb + F * ezp;
             den = den + F;
             const double Ae = (e_c * den - nb) / f.h2;
-            b1[c] = (T)((double)b[c] - Ae);
+            b1[oc] = (T)((double)b[oc] - Ae);
         }
     }
 }
@@ -951,8 +1115,16 @@ __device__ inline long long fidx(const Grid &g, int i, int j, int k)
 
 // Face coefficient below cell (i,j,k) along axis ax (either side may be a
 // ghost; i,j,k may equal n along ax).
+// Storage index of cell (i, j, k) of a level (natural, or colour-split on a
+// split finest level).
+__device__ inline long long cell_at(const Grid &g, int i, int j, int k, bool sp)
+{
+    const long long c = ((long long)i * g.ny + j) * g.nz + k;
+    return sp ? sidx(c, (i + j + k) & 1) : c;
+}
+
 template <typename T>
-__device__ inline T face_below(const Grid &g, int ax, int i, int j, int k)
+__device__ inline T face_below(const Grid &g, int ax, int i, int j, int k, bool sp = false)
 {
     if (!g.fine) {
         const long long nf = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
@@ -963,10 +1135,9 @@ __device__ inline T face_below(const Grid &g, int ax, int i, int j, int k)
     if (ax == 0) li -= 1; else if (ax == 1) lj -= 1; else lk -= 1;
     const bool hi_in = i < g.nx && j < g.ny && k < g.nz;
     const bool lo_in = li >= 0 && lj >= 0 && lk >= 0;
-    const long long sx = (long long)g.ny * g.nz;
     if (hi_in && lo_in)
-        return (T)0.5 * (D[i * sx + (long long)j * g.nz + k] + D[li * sx + (long long)lj * g.nz + lk]);
-    const T Din = hi_in ? D[i * sx + (long long)j * g.nz + k] : D[li * sx + (long long)lj * g.nz + lk];
+        return (T)0.5 * (D[cell_at(g, i, j, k, sp)] + D[cell_at(g, li, lj, lk, sp)]);
+    const T Din = hi_in ? D[cell_at(g, i, j, k, sp)] : D[cell_at(g, li, lj, lk, sp)];
     return (T)0.5 * (Din + (g.mirror ? Din : (T)g.dghost));
 }
 
@@ -980,28 +1151,32 @@ __device__ inline void cell_num_den(const Grid &g, const T *e, long long c, int 
     const T h2 = (T)g.h2;
     const T *__restrict__ D = (const T *)g.D;
     const long long sx = (long long)g.ny * g.nz, sy = g.nz;
-    const T Dc = D[c];
+    // storage index of the cell / of a neighbour (the other colour)
+    const int qc = (i + j + k) & 1;
+    const long long oc = g.split ? sidx(c, qc) : c;
+    auto at = [&](long long x) { return g.split ? sidx(x, qc ^ 1) : x; };
+    const T Dc = D[oc];
     const T gD = g.mirror ? Dc : (T)g.dghost;
-    T n_ = ((const T *)g.b)[c] * h2;
-    T d_ = ((const T *)g.sa)[c] * h2;
+    T n_ = ((const T *)g.b)[oc] * h2;
+    T d_ = ((const T *)g.sa)[oc] * h2;
     T F;
-    F = (T)0.5 * (Dc + (i > 0 ? D[c - sx] : gD));
-    n_ = n_ + F * (i > 0 ? e[c - sx] : (T)0);
+    F = (T)0.5 * (Dc + (i > 0 ? D[at(c - sx)] : gD));
+    n_ = n_ + F * (i > 0 ? e[at(c - sx)] : (T)0);
     d_ = d_ + F;
-    F = (T)0.5 * (Dc + (i < g.nx - 1 ? D[c + sx] : gD));
-    n_ = n_ + F * (i < g.nx - 1 ? e[c + sx] : (T)0);
+    F = (T)0.5 * (Dc + (i < g.nx - 1 ? D[at(c + sx)] : gD));
+    n_ = n_ + F * (i < g.nx - 1 ? e[at(c + sx)] : (T)0);
     d_ = d_ + F;
-    F = (T)0.5 * (Dc + (j > 0 ? D[c - sy] : gD));
-    n_ = n_ + F * (j > 0 ? e[c - sy] : (T)0);
+    F = (T)0.5 * (Dc + (j > 0 ? D[at(c - sy)] : gD));
+    n_ = n_ + F * (j > 0 ? e[at(c - sy)] : (T)0);
     d_ = d_ + F;
-    F = (T)0.5 * (Dc + (j < g.ny - 1 ? D[c + sy] : gD));
-    n_ = n_ + F * (j < g.ny - 1 ? e[c + sy] : (T)0);
+    F = (T)0.5 * (Dc + (j < g.ny - 1 ? D[at(c + sy)] : gD));
+    n_ = n_ + F * (j < g.ny - 1 ? e[at(c + sy)] : (T)0);
     d_ = d_ + F;
-    F = (T)0.5 * (Dc + (k > 0 ? D[c - 1] : gD));
-    n_ = n_ + F * (k > 0 ? e[c - 1] : (T)0);
+    F = (T)0.5 * (Dc + (k > 0 ? D[at(c - 1)] : gD));
+    n_ = n_ + F * (k > 0 ? e[at(c - 1)] : (T)0);
     d_ = d_ + F;
-    F = (T)0.5 * (Dc + (k < g.nz - 1 ? D[c + 1] : gD));
-    n_ = n_ + F * (k < g.nz - 1 ? e[c + 1] : (T)0);
+    F = (T)0.5 * (Dc + (k < g.nz - 1 ? D[at(c + 1)] : gD));
+    n_ = n_ + F * (k < g.nz - 1 ? e[at(c + 1)] : (T)0);
     d_ = d_ + F;
     num = n_;
     den = d_;
@@ -1065,6 +1240,15 @@ k_zero(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         if (active && !active[g.prob])
             continue;
         T *e = (T *)g.e;
+        if (g.split) {
+            // the task's cells: compact run [start/2, (start+count)/2), both colours
+            const long long m0 = tk.start >> 1;
+            for (int q = threadIdx.x; q < (tk.count >> 1); q += blockDim.x) {
+                e[cpos(m0 + q, 0)] = (T)0;
+                e[cpos(m0 + q, 1)] = (T)0;
+            }
+            continue;
+        }
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x)
             e[tk.start + q] = (T)0;
     }
@@ -1074,9 +1258,12 @@ k_zero(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 // other colour): e_p <- w num/den + (1-w) e_p.  Smoothed levels have even
 // dimensions; a task's cells pair up along z and each thread updates the
 // cell of the requested colour in its pair.
+// Red-black half-sweep of the level smoother.  The finest level (cell D,
+// face coefficients formed on the fly) and the coarse levels (stored Galerkin
+// faces) are separate kernels, so profiles can tell them apart.
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour, T omega)
+__device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *tasks, int ntasks,
+                                             const int *active, int colour, T omega)
 {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
@@ -1086,7 +1273,105 @@ k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, in
         T *e = (T *)g.e;
         const Dec dec(g.ny, g.nz);
         const int npairs = tk.count >> 1;
-        if (g.fine && (g.nz & 3) == 0) {
+        if (g.split) {
+            // colour-split finest level: the task's cells of this colour are
+            // the compact run [start/2, (start+count)/2); a thread updates 4
+            // of them (8 cells of one z row, k0 % 8 == 0), one 16-byte run of
+            // each array.  Their x/y neighbours sit at the same compact places
+            // of the other colour, their z neighbours one place to the left or
+            // right.
+            const T *__restrict__ Dall = (const T *)g.D;
+            const T *__restrict__ bb = (const T *)g.b;
+            const T *__restrict__ sa = (const T *)g.sa;
+            const int oc = colour ^ 1;
+            const long long hx = ((long long)g.ny * g.nz) >> 1, hy = g.nz >> 1;
+            const T h2 = (T)g.h2;
+            const T dgh = (T)g.dghost;
+            const bool blend = omega != (T)1;
+            for (int q = threadIdx.x; q < (tk.count >> 3); q += blockDim.x) {
+                const long long c0 = tk.start + 8 * (long long)q;
+                const long long m0 = c0 >> 1;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                // this colour's cells: k = k0 + o + 2a, a = 0..3
+                const int o = (colour ^ i ^ j) & 1;
+                T X[4], DX[4], Dc[4], bq[4], saq[4];
+                T xm[4] = {}, xp[4] = {}, ym[4] = {}, yp[4] = {}, own[4] = {};
+                T Dxm[4] = {}, Dxp[4] = {}, Dym[4] = {}, Dyp[4] = {};
+                const long long so = cpos(m0, colour), sx_ = cpos(m0, oc);
+                ld4(e + sx_, X);
+                ld4(Dall + sx_, DX);
+                ld4(Dall + so, Dc);
+                ld4(bb + so, bq);
+                ld4(sa + so, saq);
+                if (blend)
+                    ld4(e + so, own);
+                if (i > 0) {
+                    const long long x = cpos(m0 - hx, oc);
+                    ld4(e + x, xm);
+                    ld4(Dall + x, Dxm);
+                }
+                if (i < g.nx - 1) {
+                    const long long x = cpos(m0 + hx, oc);
+                    ld4(e + x, xp);
+                    ld4(Dall + x, Dxp);
+                }
+                if (j > 0) {
+                    const long long x = cpos(m0 - hy, oc);
+                    ld4(e + x, ym);
+                    ld4(Dall + x, Dym);
+                }
+                if (j < g.ny - 1) {
+                    const long long x = cpos(m0 + hy, oc);
+                    ld4(e + x, yp);
+                    ld4(Dall + x, Dyp);
+                }
+                // the z neighbour outside the loaded run: left (o = 0) or right
+                T ez = (T)0, Dz = (T)0;
+                if (o == 0 && k0 > 0) {
+                    const long long x = cpos(m0 - 1, oc);
+                    ez = e[x];
+                    Dz = Dall[x];
+                }
+                if (o == 1 && k0 + 8 < g.nz) {
+                    const long long x = cpos(m0 + 4, oc);
+                    ez = e[x];
+                    Dz = Dall[x];
+                }
+                T out[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int k = k0 + o + 2 * a;
+                    const T Dp = Dc[a];
+                    const T gD = g.mirror ? Dp : dgh;
+                    T ezm, Dzm, ezp, Dzp;
+                    if (o) {
+                        ezm = X[a]; Dzm = DX[a];
+                        ezp = a < 3 ? X[a + 1] : ez; Dzp = a < 3 ? DX[a + 1] : Dz;
+                    } else {
+                        ezm = a > 0 ? X[a - 1] : ez; Dzm = a > 0 ? DX[a - 1] : Dz;
+                        ezp = X[a]; Dzp = DX[a];
+                    }
+                    T n_ = bq[a] * h2;
+                    T d_ = saq[a] * h2;
+                    T F;
+                    F = (T)0.5 * (Dp + (i > 0 ? Dxm[a] : gD));
+                    n_ = n_ + F * (i > 0 ? xm[a] : (T)0); d_ = d_ + F;
+                    F = (T)0.5 * (Dp + (i < g.nx - 1 ? Dxp[a] : gD));
+                    n_ = n_ + F * (i < g.nx - 1 ? xp[a] : (T)0); d_ = d_ + F;
+                    F = (T)0.5 * (Dp + (j > 0 ? Dym[a] : gD));
+                    n_ = n_ + F * (j > 0 ? ym[a] : (T)0); d_ = d_ + F;
+                    F = (T)0.5 * (Dp + (j < g.ny - 1 ? Dyp[a] : gD));
+                    n_ = n_ + F * (j < g.ny - 1 ? yp[a] : (T)0); d_ = d_ + F;
+                    F = (T)0.5 * (Dp + (k > 0 ? Dzm : gD));
+                    n_ = n_ + F * (k > 0 ? ezm : (T)0); d_ = d_ + F;
+                    F = (T)0.5 * (Dp + (k < g.nz - 1 ? Dzp : gD));
+                    n_ = n_ + F * (k < g.nz - 1 ? ezp : (T)0); d_ = d_ + F;
+                    out[a] = omega * (n_ / d_) + ((T)1 - omega) * own[a];
+                }
+                st4(e + so, out);
+            }
+        } else if (g.fine && (g.nz & 3) == 0) {
             const T *__restrict__ D = (const T *)g.D;
             const T *__restrict__ bb = (const T *)g.b;
             const T *__restrict__ sa = (const T *)g.sa;
@@ -1152,9 +1437,24 @@ k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, in
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_smooth_fine(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour,
+              T omega)
+{
+    smooth_tasks<T>(grids, tasks, ntasks, active, colour, omega);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour, T omega)
+{
+    smooth_tasks<T>(grids, tasks, ntasks, active, colour, omega);
+}
+
 // Coarse right-hand side = 8-child mean of the fine residual b - A e.
 // Tasks run over the cells of the coarse grid.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 {
@@ -1164,6 +1464,7 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         if (active && !active[C.prob])
             continue;
         const Grid &F = grids[C.finer];
+        const bool sp = grid_split<SP>(F);
         const T *e = (const T *)F.e;
         T *bc = (T *)C.b;
         const T h2 = (T)F.h2;
@@ -1175,10 +1476,11 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
             const T *__restrict__ bf = (const T *)F.b;
             const T *__restrict__ sa = (const T *)F.sa;
             const long long sx = (long long)F.ny * F.nz, sy = F.nz;
-            auto E4 = [&](long long x, T v[4]) { ld4(e + x, v); };
-            auto E1 = [&](long long x) { return e[x]; };
-            auto D4 = [&](long long x, T v[4]) { ld4(D + x, v); };
-            auto D1 = [&](long long x) { return D[x]; };
+                QuadSrc<T> Es{e, 0, 0, sp}, Ds{D, 0, 0, sp};
+            auto E4 = [&](long long x, T v[4]) { Es.quad(x, v); };
+            auto E1 = [&](long long x) { return Es.one(x); };
+            auto D4 = [&](long long x, T v[4]) { Ds.quad(x, v); };
+            auto D1 = [&](long long x) { return Ds.one(x); };
             for (int q = threadIdx.x; q < (tk.count >> 1); q += blockDim.x) {
                 const long long cc = tk.start + 2 * (long long)q;
                 int I, J, K;
@@ -1189,12 +1491,20 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
                         const int di = dd >> 1, dj = dd & 1;
                         const int i = 2 * I + di, j = 2 * J + dj, k0 = 2 * K;
                         const long long c0 = ((long long)i * F.ny + j) * F.nz + k0;
+                        const int q0 = (i + j) & 1;
+                        Es.c0 = Ds.c0 = c0;
+                        Es.q0 = Ds.q0 = q0;
                         Hood<T> Eh, Dh;
                         gather(Eh, E4, E1, c0, i, j, k0, F.nx, F.ny, F.nz, sx, sy, (T)0);
                         gather(Dh, D4, D1, c0, i, j, k0, F.nx, F.ny, F.nz, sx, sy, (T)F.dghost);
                         T bq[4], saq[4], r[4];
-                        ld4(bf + c0, bq);
-                        ld4(sa + c0, saq);
+                        if (sp) {
+                            ld4s(bf, c0, q0, bq);
+                            ld4s(sa, c0, q0, saq);
+                        } else {
+                            ld4(bf + c0, bq);
+                            ld4(sa + c0, saq);
+                        }
 #pragma unroll
                         for (int m = 0; m < 4; ++m) {
                             T Fc[6];
@@ -1231,7 +1541,7 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
                         const long long c = ((long long)i * F.ny + j) * F.nz + k;
                         T num, den;
                         level_num_den<T>(F, e, c, i, j, k, num, den);
-                        s = s + (num - e[c] * den) / h2;
+                        s = s + (num - e[sp ? cell_at(F, i, j, k, true) : c] * den) / h2;
                     }
             bc[cc] = (T)0.125 * s;
         }
@@ -1239,7 +1549,7 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 }
 
 // e_fine += e_coarse(parent).  Tasks run over the cells of the fine grid.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 {
@@ -1249,6 +1559,7 @@ k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         if (active && !active[F.prob])
             continue;
         const Grid &C = grids[F.coarser];
+        const bool sp = grid_split<SP>(F);
         T *ef = (T *)F.e;
         const T *ec = (const T *)C.e;
         const Dec dec(F.ny, F.nz);
@@ -1256,7 +1567,8 @@ k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
             const long long c = tk.start + q;
             int i, j, k;
             dec(c, i, j, k);
-            ef[c] = ef[c] + ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
+            const long long o = sp ? sidx(c, (i + j + k) & 1) : c;
+            ef[o] = ef[o] + ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
         }
     }
 }
@@ -1264,7 +1576,7 @@ k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 // Galerkin coarse faces: half the sum of the four fine faces on each coarse
 // face (in-face indices in lexicographic order).  Tasks run over the padded
 // (nx+1)(ny+1)(nz+1) face grid of the coarse level.
-template <typename T>
+template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 {
@@ -1274,6 +1586,7 @@ k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         if (active && !active[C.prob])
             continue;
         const Grid &F = grids[C.finer];
+        const bool sp = grid_split<SP>(F);
         T *fc = (T *)C.f;
         const long long nf = (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
         const Dec dec(C.ny + 1, C.nz + 1);
@@ -1285,30 +1598,30 @@ k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
             T v = (T)0;
             if (J < C.ny && K < C.nz) {
                 T s = (T)0;
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K);
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K + 1);
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K);
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K + 1);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K, sp);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K + 1, sp);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K, sp);
+                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K + 1, sp);
                 v = (T)0.5 * s;
             }
             fc[c] = v;
             v = (T)0;
             if (I < C.nx && K < C.nz) {
                 T s = (T)0;
-                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K);
-                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K + 1);
-                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K);
-                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K + 1);
+                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K, sp);
+                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K + 1, sp);
+                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K, sp);
+                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K + 1, sp);
                 v = (T)0.5 * s;
             }
             fc[nf + c] = v;
             v = (T)0;
             if (I < C.nx && J < C.ny) {
                 T s = (T)0;
-                s = s + face_below<T>(F, 2, 2 * I, 2 * J, 2 * K);
-                s = s + face_below<T>(F, 2, 2 * I, 2 * J + 1, 2 * K);
-                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J, 2 * K);
-                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J + 1, 2 * K);
+                s = s + face_below<T>(F, 2, 2 * I, 2 * J, 2 * K, sp);
+                s = s + face_below<T>(F, 2, 2 * I, 2 * J + 1, 2 * K, sp);
+                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J, 2 * K, sp);
+                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J + 1, 2 * K, sp);
                 v = (T)0.5 * s;
             }
             fc[2 * nf + c] = v;
@@ -1335,69 +1648,83 @@ k_mean8_sa(const Grid *grids, const Task *tasks, int ntasks)
             for (int di = 0; di < 2; ++di)
                 for (int dj = 0; dj < 2; ++dj)
                     for (int dk = 0; dk < 2; ++dk)
-                        s = s + sf[((long long)(2 * I + di) * F.ny + (2 * J + dj)) * F.nz + (2 * K + dk)];
+                        s = s + sf[cell_at(F, 2 * I + di, 2 * J + dj, 2 * K + dk, F.split)];
             sc[cc] = (T)0.125 * s;
         }
     }
 }
 
-// Coarsest level: banded Cholesky of M = h^2 A (natural order, half
-// bandwidth bw = ny*nz), FP64.  Band entry (r, q), r - bw <= q <= r, sits at
-// band[r*(bw+1) + q - r + bw].  Right-looking: after column c is scaled,
-// every entry of the trailing band subtracts L(r,c) L(q,c); each entry thus
-// receives its subtractions in ascending column order, the order of the
-// textbook (left-looking) recurrence.  The band is factored in LDS when it
-// fits (kCholLds bytes) and in global memory otherwise.
+// Coarsest level: e = M^{-1} (h^2 b) with M = h^2 A in natural order (half
+// bandwidth bw = ny*nz), factored by banded Cholesky in FP64 and solved in the
+// same launch.  Band entry (r, q), r - bw <= q <= r, sits at
+// band[r*(bw+1) + q - r + bw].  The factor is right-looking: after column c is
+// scaled, every entry of the trailing band subtracts L(r,c) L(q,c), so each
+// entry receives its subtractions in ascending column order, the order of the
+// textbook recurrence.  The forward substitution subtracts column by column
+// (again ascending) and the backward one row by row in ascending order, so
+// every value is rounded as in the textbook dense algorithm.  The band lives
+// in LDS when it fits (kCholLds bytes), else in global memory; a block of one
+// wavefront keeps the per-column barriers cheap.
 constexpr int kCholLds = 64 * 1024;
+
+// LDS: y and a row of products (2 max_n doubles), then the band if it fits.
+__host__ __device__ inline bool chol_in_lds(long long n, long long bw, long long max_n)
+{
+    return n * (bw + 1) * 8 + 2 * max_n * 8 <= kCholLds;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_chol_factor(const Grid *grids, const int *ids, const int *active, int *fail)
+k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, int max_n)
 {
     extern __shared__ double lds[];
     const Grid &g = grids[ids[blockIdx.x]];
     if (active && !active[g.prob])
         return;
     const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
-    const bool in_lds = (long long)n * W * 8 <= kCholLds;
-    double *L = in_lds ? lds : g.band;
+    double *y = lds;
+    double *L = chol_in_lds(n, bw, max_n) ? lds + 2 * max_n : g.band;
     const double h2 = g.h2;
     const T *sa = (const T *)g.sa;
+    const T *b = (const T *)g.b;
+    T *e = (T *)g.e;
     const Dec dec(g.ny, g.nz);
-    for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x) {
-        const int r = (int)(x / W), d = (int)(x - (long long)r * W);
-        const int q = r - bw + d;
-        double v = 0.0;
+    // assemble: one row per thread, its face loads independent of each other
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
         int i, j, k;
         dec(r, i, j, k);
-        if (q == r) {
-            v = (double)sa[r] * h2;
-            v = v + (double)face_below<T>(g, 0, i, j, k);
-            v = v + (double)face_below<T>(g, 0, i + 1, j, k);
-            v = v + (double)face_below<T>(g, 1, i, j, k);
-            v = v + (double)face_below<T>(g, 1, i, j + 1, k);
-            v = v + (double)face_below<T>(g, 2, i, j, k);
-            v = v + (double)face_below<T>(g, 2, i, j, k + 1);
-        } else if (q >= 0) {
-            const int off = r - q;
-            if (off == 1 && k > 0)
-                v = -(double)face_below<T>(g, 2, i, j, k);
-            else if (off == g.nz && j > 0)
-                v = -(double)face_below<T>(g, 1, i, j, k);
-            else if (off == bw && i > 0)
-                v = -(double)face_below<T>(g, 0, i, j, k);
-        }
-        L[x] = v;
+        double *row = L + (long long)r * W;       // row[q - r + bw]
+        const double fx0 = (double)face_below<T>(g, 0, i, j, k);
+        const double fx1 = (double)face_below<T>(g, 0, i + 1, j, k);
+        const double fy0 = (double)face_below<T>(g, 1, i, j, k);
+        const double fy1 = (double)face_below<T>(g, 1, i, j + 1, k);
+        const double fz0 = (double)face_below<T>(g, 2, i, j, k);
+        const double fz1 = (double)face_below<T>(g, 2, i, j, k + 1);
+        for (int d = 0; d < bw; ++d)
+            row[d] = 0.0;
+        double v = (double)sa[r] * h2;
+        v = v + fx0;
+        v = v + fx1;
+        v = v + fy0;
+        v = v + fy1;
+        v = v + fz0;
+        v = v + fz1;
+        row[bw] = v;
+        if (k > 0)
+            row[bw - 1] = -fz0;
+        if (j > 0)
+            row[bw - g.nz] = -fy0;
+        if (i > 0)
+            row[0] = -fx0;
+        y[r] = (double)b[r] * h2;
     }
-    __shared__ int bad;
-    if (threadIdx.x == 0)
-        bad = 0;
     __syncthreads();
+    // factor
+    bool bad = false;
     for (int c = 0; c < n; ++c) {
         if (threadIdx.x == 0) {
             const double d = L[(long long)c * W + bw];
-            if (!(d > 0.0))
-                bad = 1;
+            bad = bad || !(d > 0.0);
             L[(long long)c * W + bw] = sqrt(d);
         }
         __syncthreads();
@@ -1408,11 +1735,17 @@ k_chol_factor(const Grid *grids, const int *ids, const int *active, int *fail)
             L[(long long)r * W + c - r + bw] = L[(long long)r * W + c - r + bw] / lcc;
         }
         __syncthreads();
-        for (int x = threadIdx.x; x < m * m; x += blockDim.x) {
-            const int a = x / m, b = x - a * m;      // r = c+1+a, q = c+1+b, q <= r
-            if (b > a)
-                continue;
-            const int r = c + 1 + a, q = c + 1 + b;
+        // trailing entries (r, q) = (c+1+a, c+1+bb), 0 <= bb <= a < m, enumerated
+        // row by row: x = a(a+1)/2 + bb
+        const int np = m * (m + 1) / 2;
+        for (int x = threadIdx.x; x < np; x += blockDim.x) {
+            int a = (int)((sqrtf(8.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
+            if ((a + 1) * (a + 2) / 2 <= x)
+                ++a;
+            if (a * (a + 1) / 2 > x)
+                --a;
+            const int bb = x - a * (a + 1) / 2;
+            const int r = c + 1 + a, q = c + 1 + bb;
             const double lrc = L[(long long)r * W + c - r + bw];
             const double lqc = L[(long long)q * W + c - q + bw];
             double &t = L[(long long)r * W + q - r + bw];
@@ -1420,59 +1753,36 @@ k_chol_factor(const Grid *grids, const int *ids, const int *active, int *fail)
         }
         __syncthreads();
     }
-    if (in_lds)
-        for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x)
-            g.band[x] = L[x];
     if (threadIdx.x == 0 && bad)
         fail[g.prob] = 1;
-}
-
-// Forward/backward substitution with the band factor (staged in LDS when it
-// fits); the inner products are split over the first wave and reduced with
-// shuffles.
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_chol_solve(const Grid *grids, const int *ids, const int *active, int max_n)
-{
-    extern __shared__ double lds[];
-    const Grid &g = grids[ids[blockIdx.x]];
-    if (active && !active[g.prob])
-        return;
-    const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
-    double *y = lds;
-    const bool in_lds = (long long)n * W * 8 + (long long)max_n * 8 <= kCholLds;
-    double *L = in_lds ? lds + max_n : g.band;
-    if (in_lds)
-        for (long long x = threadIdx.x; x < (long long)n * W; x += blockDim.x)
-            L[x] = g.band[x];
-    const T *b = (const T *)g.b;
-    T *e = (T *)g.e;
-    for (int r = threadIdx.x; r < n; r += blockDim.x)
-        y[r] = (double)b[r] * g.h2;
-    __syncthreads();
-    const int lane = threadIdx.x;
-    for (int r = 0; r < n; ++r) {
-        if (lane < kWave) {
-            double part = 0.0;
-            for (int q = (r - bw > 0 ? r - bw : 0) + lane; q < r; q += kWave)
-                part += L[(long long)r * W + q - r + bw] * y[q];
-            for (int o = kWave / 2; o > 0; o >>= 1)
-                part += __shfl_xor(part, o, kWave);
-            if (lane == 0)
-                y[r] = (y[r] - part) / L[(long long)r * W + bw];
+    // L y = h^2 b, column by column
+    for (int c = 0; c < n; ++c) {
+        if (threadIdx.x == 0)
+            y[c] = y[c] / L[(long long)c * W + bw];
+        __syncthreads();
+        const double yc = y[c];
+        const int m = (c + bw < n - 1) ? bw : n - 1 - c;
+        for (int a = threadIdx.x; a < m; a += blockDim.x) {
+            const int r = c + 1 + a;
+            y[r] = y[r] - L[(long long)r * W + c - r + bw] * yc;
         }
         __syncthreads();
     }
+    // L^T x = y, row by row: the products in parallel, their subtraction in
+    // ascending order by one lane
+    double *prod = y + n;
     for (int r = n - 1; r >= 0; --r) {
-        if (lane < kWave) {
-            double part = 0.0;
-            const int qmax = (r + bw < n - 1) ? r + bw : n - 1;
-            for (int q = r + 1 + lane; q <= qmax; q += kWave)
-                part += L[(long long)q * W + r - q + bw] * y[q];
-            for (int o = kWave / 2; o > 0; o >>= 1)
-                part += __shfl_xor(part, o, kWave);
-            if (lane == 0)
-                y[r] = (y[r] - part) / L[(long long)r * W + bw];
+        const int m = (r + bw < n - 1) ? bw : n - 1 - r;
+        for (int a = threadIdx.x; a < m; a += blockDim.x) {
+            const int q = r + 1 + a;
+            prod[a] = L[(long long)q * W + r - q + bw] * y[q];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = y[r];
+            for (int a = 0; a < m; ++a)
+                s = s - prod[a];
+            y[r] = s / L[(long long)r * W + bw];
         }
         __syncthreads();
     }
@@ -1492,6 +1802,16 @@ inline int grid_for(int ntasks)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+// Kernel instance for a precision/layout mode: 0 FP64, 1 FP32 natural,
+// 2 FP32 colour-split, 3 FP32 decided per problem (instances share one
+// signature).
+#define FLD_PICK(K, mode)                                                      \
+    ((mode) == 0 ? K<double, 0>                                                \
+                 : (mode) == 1 ? K<float, 0> : (mode) == 2 ? K<float, 1> : K<float, 2>)
+// Level kernels: the precision is the template's, sp is 0/1/2 as above.
+#define FLD_PICK_SP(K, T, sp)                                                  \
+    (sizeof(T) == 8 || (sp) == 0 ? K<T, 0> : (sp) == 1 ? K<T, 1> : K<T, 2>)
 
 void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
                   const double *sigma_t, const double *albedo, const double *Q,
@@ -1529,11 +1849,7 @@ void launch_limiter(hipStream_t s, const Fine *fines, const Task *tasks, int nta
                     const int *active, const double *scal, int src, int dst, int use_dir,
                     int dir_idx, int to_tmp, int mixed)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_limiter<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, scal, src, dst, use_dir, dir_idx, to_tmp);
-    else
-        hipLaunchKernelGGL(k_limiter<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_limiter, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, scal, src, dst, use_dir, dir_idx, to_tmp);
 }
 
@@ -1541,11 +1857,7 @@ void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      const int *active, int src, int use_tmp, int b0_idx, double *r_out,
                      double *partials, int mixed)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_residual<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, src, use_tmp, b0_idx, r_out, partials);
-    else
-        hipLaunchKernelGGL(k_residual<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_residual, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, src, use_tmp, b0_idx, r_out, partials);
 }
 
@@ -1558,11 +1870,7 @@ void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int n
                       const int *active, int b0_idx, double *pg, double *ps,
                       const double *alpha, int mixed)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_npcg_dots<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, b0_idx, pg, ps, alpha);
-    else
-        hipLaunchKernelGGL(k_npcg_dots<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_npcg_dots, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, b0_idx, pg, ps, alpha);
 }
 
@@ -1571,11 +1879,7 @@ void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int n
 {
     if (nct <= 0)
         return;
-    if (mixed)
-        hipLaunchKernelGGL(k_defl_reduce<float>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
-                           ct, nct, active, b0_idx, pd, ps);
-    else
-        hipLaunchKernelGGL(k_defl_reduce<double>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_defl_reduce, mixed), dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
                            ct, nct, active, b0_idx, pd, ps);
 }
 
@@ -1590,11 +1894,7 @@ void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const i
 void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                        const int *active, int b0_idx, const double *alpha, int mixed)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_defl_apply<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, b0_idx, alpha);
-    else
-        hipLaunchKernelGGL(k_defl_apply<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_defl_apply, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, b0_idx, alpha);
 }
 
@@ -1608,11 +1908,7 @@ void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      const int *active, const double *scal, int b0_idx, int pin, int pout,
                      double *prp, double *ppap, int mixed)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_npcg_dir<float>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, scal, b0_idx, pin, pout, prp, ppap);
-    else
-        hipLaunchKernelGGL(k_npcg_dir<double>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_npcg_dir, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, scal, b0_idx, pin, pout, prp, ppap);
 }
 
@@ -1638,34 +1934,34 @@ void launch_zero(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks
 
 template <typename T>
 void launch_smooth(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                   const int *active, int colour, double omega)
+                   const int *active, int colour, double omega, bool finest)
 {
-    hipLaunchKernelGGL(k_smooth<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
-                       ntasks, active, colour, (T)omega);
+    hipLaunchKernelGGL(finest ? k_smooth_fine<T> : k_smooth<T>, dim3(grid_for(ntasks)),
+                       dim3(kBlock), 0, s, grids, tasks, ntasks, active, colour, (T)omega);
 }
 
 template <typename T>
 void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                     const int *active)
+                     const int *active, int sp)
 {
-    hipLaunchKernelGGL(k_restrict<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
-                       ntasks, active);
+    hipLaunchKernelGGL(FLD_PICK_SP(k_restrict, T, sp), dim3(grid_for(ntasks)), dim3(kBlock), 0, s,
+                       grids, tasks, ntasks, active);
 }
 
 template <typename T>
 void launch_prolong(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                    const int *active)
+                    const int *active, int sp)
 {
-    hipLaunchKernelGGL(k_prolong<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
-                       ntasks, active);
+    hipLaunchKernelGGL(FLD_PICK_SP(k_prolong, T, sp), dim3(grid_for(ntasks)), dim3(kBlock), 0, s,
+                       grids, tasks, ntasks, active);
 }
 
 template <typename T>
 void launch_galerkin(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                     const int *active)
+                     const int *active, int sp)
 {
-    hipLaunchKernelGGL(k_galerkin<T>, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, grids, tasks,
-                       ntasks, active);
+    hipLaunchKernelGGL(FLD_PICK_SP(k_galerkin, T, sp), dim3(grid_for(ntasks)), dim3(kBlock), 0, s,
+                       grids, tasks, ntasks, active);
 }
 
 template <typename T>
@@ -1676,35 +1972,26 @@ void launch_mean8_sa(hipStream_t s, const Grid *grids, const Task *tasks, int nt
 }
 
 template <typename T>
-void launch_chol_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
-                        const int *active, int *fail)
+void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
+                         const int *active, int *fail, int max_n, int max_bw)
 {
+    // one wavefront while the band fits in LDS, a full block otherwise
+    const int threads = chol_in_lds(max_n, max_bw, max_n) ? kWave : kBlock;
     if (count > 0)
-        hipLaunchKernelGGL(k_chol_factor<T>, dim3(count), dim3(kBlock), kCholLds, s, grids, ids,
-                           active, fail);
-}
-
-template <typename T>
-void launch_chol_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
-                       const int *active, int max_n)
-{
-    if (count > 0)
-        hipLaunchKernelGGL(k_chol_solve<T>, dim3(count), dim3(kBlock), kCholLds, s, grids, ids,
-                           active, max_n);
+        hipLaunchKernelGGL(k_coarse_solve<T>, dim3(count), dim3(threads), kCholLds, s, grids, ids,
+                           active, fail, max_n);
 }
 
 #define FLD_INSTANTIATE(T)                                                                       \
     template void launch_zero<T>(hipStream_t, const Grid *, const Task *, int, const int *);     \
     template void launch_smooth<T>(hipStream_t, const Grid *, const Task *, int, const int *,    \
-                                   int, double);                                                 \
-    template void launch_restrict<T>(hipStream_t, const Grid *, const Task *, int, const int *); \
-    template void launch_prolong<T>(hipStream_t, const Grid *, const Task *, int, const int *);  \
-    template void launch_galerkin<T>(hipStream_t, const Grid *, const Task *, int, const int *); \
+                                   int, double, bool);                                           \
+    template void launch_restrict<T>(hipStream_t, const Grid *, const Task *, int, const int *, int); \
+    template void launch_prolong<T>(hipStream_t, const Grid *, const Task *, int, const int *, int);  \
+    template void launch_galerkin<T>(hipStream_t, const Grid *, const Task *, int, const int *, int); \
     template void launch_mean8_sa<T>(hipStream_t, const Grid *, const Task *, int);              \
-    template void launch_chol_factor<T>(hipStream_t, const Grid *, const int *, int, const int *, \
-                                        int *);                                                  \
-    template void launch_chol_solve<T>(hipStream_t, const Grid *, const int *, int, const int *, \
-                                       int);
+    template void launch_coarse_solve<T>(hipStream_t, const Grid *, const int *, int,            \
+                                         const int *, int *, int, int);
 
 FLD_INSTANTIATE(float)
 FLD_INSTANTIATE(double)

@@ -246,3 +246,61 @@ def test_graph_replay_is_bit_identical():
     for phi, rep in outs[1:]:
         np.testing.assert_array_equal(phi, outs[0][0])
         np.testing.assert_array_equal(rep["history"], outs[0][1]["history"])
+    # events recorded inside the graphs time the same launches as eager ones
+    assert outs[3][1]["kernel_launches"] == outs[1][1]["kernel_launches"]
+    assert outs[3][1]["kernel_bytes"] == outs[1][1]["kernel_bytes"]
+    # finest half-sweep in FP32: black e, all of D, red b and sa, red e written
+    rep = outs[1][1]
+    assert rep["kernel_bytes"][0] == rep["kernel_launches"][0] * 12.0 * st.size
+
+
+@pytest.mark.parametrize("shape,omega_s", [((32, 32, 32), 1.0), ((24, 16, 40), 1.0),
+                                           ((16, 16, 8), 1.0), ((32, 24, 16), 1.2)])
+def test_colour_split_is_bit_identical(shape, omega_s):
+    # the red/black storage of the finest FP32 fields changes where values
+    # live, not how they are computed
+    st, al, Q, h = ragged_cloud(shape, seed=7)
+    outs = []
+    for split in (0, 1):
+        s = gpu_solver(shape, h, st, al, Q, precision="mixed", tol=0.0, max_iters=8,
+                       omega_s=omega_s, colour_split=split)
+        outs.append(s.solve())
+    np.testing.assert_array_equal(outs[1][0], outs[0][0])
+    np.testing.assert_array_equal(outs[1][1]["history"], outs[0][1]["history"])
+
+
+def test_launch_shapes_are_bit_identical():
+    st, al, Q, h = ragged_cloud((32, 32, 48), seed=9)
+    outs = []
+    for tc0, cb in ((4096, 2048), (512, 64), (65536, 65536)):
+        s = gpu_solver(st.shape, h, st, al, Q, precision="mixed", tol=0.0, max_iters=6,
+                       task_cells0=tc0, coarse_blocks=cb)
+        outs.append(s.solve())
+    for phi, rep in outs[1:]:
+        np.testing.assert_array_equal(phi, outs[0][0])
+        np.testing.assert_array_equal(rep["history"], outs[0][1]["history"])
+
+
+def test_batch_mixing_split_and_natural_volumes():
+    # nz % 8 == 0 volumes use the colour-split storage, the 24x16x20 one the
+    # natural order; one batch holds both and each result equals its own solve
+    shapes = [(16, 16, 16), (24, 16, 20), (16, 24, 32)]
+    vols = [ragged_cloud(sh, seed=20 + q) for q, sh in enumerate(shapes)]
+    albs = (0.99, 0.9)
+    o = F.fld_default_options(precision="mixed", tol=0.0, max_iters=7)
+    b = F.fld_batch_create(o, shapes, [v[3] for v in vols], len(albs))
+    for q, (st, _, _, h) in enumerate(vols):
+        al = [np.full(st.shape, a) for a in albs]
+        F.fld_batch_set_volume(b, q, st, al, [media.beer_lambert_source(st, x, h) for x in al])
+    outs, iters, rep = F.fld_batch_solve(b, [sh for sh in shapes for _ in albs])
+    F.fld_batch_destroy(b)
+    r = 0
+    for st, _, _, h in vols:
+        for a in albs:
+            al = np.full(st.shape, a)
+            s = gpu_solver(st.shape, h, st, al, media.beer_lambert_source(st, al, h),
+                           precision="mixed", tol=0.0, max_iters=7)
+            phi, rep1 = s.solve()
+            assert iters[r] == rep1["iterations"] == 7
+            np.testing.assert_array_equal(outs[r], phi)
+            r += 1
