@@ -77,7 +77,7 @@ def cpu_baseline(st, al, Q, h, budget_s=20.0):
     t1 = time.perf_counter()
     oracle.solve(prob, method="mg", tol=0.0, max_iters=1)
     t_one = time.perf_counter() - t1
-    its = max(1, min(6, int(budget_s / max(t_one, 1e-3))))
+    its = max(1, min(40, int(budget_s / max(t_one, 1e-3))))
     t2 = time.perf_counter()
     res = oracle.solve(prob, method="mg", tol=0.0, max_iters=its)
     dt = time.perf_counter() - t2
