@@ -18,8 +18,18 @@ library reports.  The HBM traffic measured by counters is read from the
 committed counter summary while the kernel source it was taken on is
 unchanged.
 
+Other workloads (`--workload`, one JSON line each; not the headline):
+  cloud128-fp64  128^3 cloud (seed 1), plain FP64 multigrid to rel 1e-8;
+  batch          16 cloud volumes of seeded sizes {64..192}^3 x 3 colour
+                 channels (albedo 0.99/0.95/0.9, shared sigma_t), one batched
+                 mixed solve to rel 1e-6; --sequential adds the same 48
+                 problems solved one at a time;
+  cloud512       512^3 cloud (7 octaves, sigma_t in [0,500], 60% near-vacuum,
+                 albedo 0.995, seed 4), mixed to rel 1e-6, solved in resumed
+                 chunks so progress is printed.
+
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-       [--no-fp64] [--max-iters M] [--copy-bytes B]
+       [--no-fp64] [--max-iters M] [--copy-bytes B] [--workload W]
 """
 import argparse
 import hashlib
@@ -119,6 +129,14 @@ def main():
                     help="skip the plain FP64 GPU solve reported beside the mixed one")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain copy of this many bytes (counter calibration)")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="ignore the autotuner's cached launch shapes and schedule")
+    ap.add_argument("--workload", default="cloud256",
+                    choices=["cloud256", "cloud128-fp64", "batch", "cloud512"])
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="outer iterations per call (0: one call); later calls resume")
+    ap.add_argument("--sequential", action="store_true",
+                    help="batch workload: also time the problems solved one at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -127,6 +145,19 @@ def main():
     if args.copy_bytes > 0:
         copy_calibration(args.copy_bytes)
         return
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.workload == "cloud128-fp64":
+        args.n, args.precision, args.tol, cfg = 128, "fp64", 1e-8, "cloud128"
+        args.no_fp64 = True
+    elif args.workload == "cloud512":
+        args.n, cfg = 512, "cloud512"
+        args.no_fp64 = args.no_cpu_baseline = True
+        args.chunk = args.chunk or 1000
+        args.max_iters = max(args.max_iters, 20000)
+    else:
+        cfg = "cloud256"
 
     import torch
     import paper_1403_8105_amd as F
@@ -134,7 +165,10 @@ def main():
 
     n = args.n
     log(f"bench: generating cloud {n}^3")
-    st, al, Q, h = media.config("cloud256", n=n)
+    st, al, Q, h = media.config(cfg, n=n)
+    desc = {"cloud256": "sigma_t in [0,200], 40% near-vacuum, albedo 0.99",
+            "cloud128": "sigma_t in [0,200], 40% near-vacuum, albedo 0.99",
+            "cloud512": "7 octaves, sigma_t in [0,500], 60% near-vacuum, albedo 0.995"}[cfg]
     dev = torch.device("cuda:0")
     d_st = torch.from_numpy(st).to(dev)
     d_al = torch.from_numpy(al).to(dev)
@@ -143,9 +177,17 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sp = stream.cuda_stream
 
+    from paper_1403_8105_amd.autotune import tuned_options
+
+    tuned = {}
+    for prec in ("mixed", "fp64"):
+        tuned[prec] = {} if args.no_tuned else tuned_options(st.shape, prec, "lp")
+        log(f"bench: {prec} options from the autotuner cache: {tuned[prec] or 'none (defaults)'}")
+
     def make(precision, timing):
-        s = F.Solver(st.shape, h, precision=precision, tol=args.tol, max_iters=args.max_iters,
-                     timing=timing, stream=sp)
+        s = F.Solver(st.shape, h, precision=precision, tol=args.tol,
+                     max_iters=args.chunk or args.max_iters, timing=timing, stream=sp,
+                     **tuned[precision])
         s.set_medium_device(d_st.data_ptr(), d_al.data_ptr(), d_Q.data_ptr(), sp)
         return s
 
@@ -153,7 +195,20 @@ def main():
     torch.cuda.synchronize()
 
     def step(s):
-        return F.fld_solve_device(s.ctx, d_phi.data_ptr())
+        """One solve to tol: one call, or resumed chunks with a progress line each."""
+        r = F.fld_solve_device(s.ctx, d_phi.data_ptr())
+        if not args.chunk:
+            return r
+        tot = dict(r)
+        while tot["status"] == F.FLD_ERR_NOT_CONVERGED and tot["iterations"] < args.max_iters:
+            log(f"bench: {tot['iterations']} iterations, rel {tot['rel']:.3e}")
+            r = F.fld_solve_device(s.ctx, d_phi.data_ptr(), resume=1)
+            for key in ("voxel_updates", "time_ms"):
+                tot[key] += r[key]
+            for key in ("kernel_ms", "kernel_launches", "kernel_bytes"):
+                tot[key] = [a + b for a, b in zip(tot[key], r[key])]
+            tot.update(status=r["status"], iterations=r["iterations"], rel=r["rel"])
+        return tot
 
     for w in range(args.warmup):
         r = step(solver)
@@ -186,10 +241,14 @@ def main():
     avg_s = kms[dom] / kl[dom] * 1e-3
     alg = kb[dom] / kl[dom]
     achieved = alg / avg_s / 1e9
-    traffic = counter_traffic()
+    # the counters were taken on the 256^3 mixed workload only
+    traffic = (counter_traffic() if args.workload == "cloud256" and args.precision == "mixed"
+               and n == 256 else None)
     ok = all(r["status"] == 0 for r in reps)
     line = {
-        "metric": "voxel-updates/s + time to 1e-6 rel. residual (256^3 FLD); % HBM peak",
+        "metric": ("voxel-updates/s + time to 1e-6 rel. residual (256^3 FLD); % HBM peak"
+                   if args.workload == "cloud256" else
+                   f"voxel-updates/s + time to {args.tol:g} rel. residual ({n}^3 FLD)"),
         "value": value,
         "unit": "voxel-updates/s",
         "n_gpus": 1,
@@ -205,10 +264,12 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32+fp64" if args.precision == "mixed" else "fp64",
         "data": "synthetic",
-        "config": {"workload": f"cloud {n}^3 FLD (Levermore-Pomraning), sigma_t in [0,200], "
-                               f"40% near-vacuum, albedo 0.99, Beer-Lambert source; "
-                               f"{args.precision} Picard multigrid V(2,2) to rel {args.tol:g}",
-                   "grid": [n, n, n], "tol": args.tol, "precision": args.precision},
+        "config": {"workload": f"cloud {n}^3 FLD (Levermore-Pomraning), {desc}, "
+                               f"Beer-Lambert source; {args.precision} Picard multigrid "
+                               f"V({tuned[args.precision].get('nu1', 2)},"
+                               f"{tuned[args.precision].get('nu2', 2)}) to rel {args.tol:g}",
+                   "grid": [n, n, n], "tol": args.tol, "precision": args.precision,
+                   "tuned_options": tuned[args.precision]},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg,
@@ -231,6 +292,73 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(st, al, Q, h)
+    print(json.dumps(line), flush=True)
+
+
+def run_batch(args):
+    """16 volumes x 3 colour channels in one batched solve (one JSON line)."""
+    import torch
+    import paper_1403_8105_amd as F
+    from paper_1403_8105_amd.autotune import tuned_options
+    from synth import media
+
+    log("bench: generating the 16-volume batch")
+    vols = media.batch_config()
+    dims = [(v["n"],) * 3 for v in vols]
+    shapes = [d for d in dims for _ in range(3)]
+    voxels = sum(a * b * c for a, b, c in dims)
+    # launch shapes and schedule of the 256^3 tuning (the batch has no entry of its own)
+    tuned = {} if args.no_tuned else tuned_options((256, 256, 256), "mixed", "lp")
+    o = F.fld_default_options(precision="mixed", tol=1e-6, max_iters=args.max_iters, **tuned)
+    b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
+    for q, v in enumerate(vols):
+        F.fld_batch_set_volume(b, q, v["sigma_t"], v["albedo"], v["Q"])
+    torch.cuda.synchronize()
+    for w in range(args.warmup):
+        _, its, r = F.fld_batch_solve(b, shapes, want_phi=False)
+        log(f"bench: batch warmup {w}: {r['time_ms']:.0f} ms, iterations {its.min()}..{its.max()}")
+    t0 = time.perf_counter()
+    reps = []
+    for k in range(args.steps):
+        _, its, r = F.fld_batch_solve(b, shapes, want_phi=False)
+        reps.append((its, r))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F.fld_batch_destroy(b)
+    its, r = reps[-1]
+    line = {
+        "metric": "voxel-updates/s + time to 1e-6 rel. residual (batched FLD, 48 problems)",
+        "value": sum(x[1]["voxel_updates"] for x in reps) / dt,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps, "time_to_tol_ms": dt * 1e3 / args.steps,
+        "converged": all(x[1]["status"] == 0 for x in reps),
+        "outer_iterations_min_max": [int(its.min()), int(its.max())],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp32+fp64", "data": "synthetic",
+        "config": {"workload": "16 cloud volumes, sizes " + ",".join(str(d[0]) for d in dims)
+                               + "^3, x 3 channels (albedo 0.99/0.95/0.9, shared sigma_t), "
+                               "mixed Picard multigrid, one batched solve to rel 1e-6",
+                   "voxels": voxels, "problems": len(shapes), "tuned_options": tuned},
+    }
+    if args.sequential:
+        log("bench: the same 48 problems one at a time")
+        seq = 0.0
+        upd = 0.0
+        for v in vols:
+            for c in range(3):
+                s = F.Solver(v["sigma_t"].shape, v["h"], precision="mixed", tol=1e-6,
+                             max_iters=args.max_iters, **tuned)
+                s.set_medium(v["sigma_t"], v["albedo"][c], v["Q"][c])
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                rr = F.fld_solve_device(s.ctx, 0)
+                torch.cuda.synchronize()
+                seq += time.perf_counter() - ta   # only the solves count
+                upd += rr["voxel_updates"]
+                s.close()
+        line["sequential_mixed"] = {"time_to_tol_ms": seq * 1e3,
+                                    "batch_speedup": seq / (dt / args.steps)}
     print(json.dumps(line), flush=True)
 
 

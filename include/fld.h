@@ -113,6 +113,9 @@ typedef struct fld_options {
                              black half, so a red-black half-sweep streams only the cells it
                              needs (used when nz % 8 == 0 and the grid coarsens; default 1).
                              Results are bit-identical to the natural order (0)            */
+    double restart_growth;/* multigrid: the conjugate-gradient direction restarts (beta = 0)
+                             after an outer iteration that raised ||r|| by more than this
+                             factor; <= 0 never restarts (default 2)                       */
 } fld_options;
 
 typedef struct fld_report {
@@ -196,6 +199,12 @@ const char *fld_status_string(fld_status s);
 
 /* Text of the last failure on c ("" if none; static "invalid context" for NULL). */
 const char *fld_last_error(const fld_context *c);
+
+/* Architecture name of HIP device `device` (for example "gfx950", without
+ * feature suffixes) into buf[0..len-1], NUL-terminated.  Used to key tuned
+ * launch options.  FLD_ERR_INVALID_ARGUMENT for a NULL buf, len < 2 or a bad
+ * ordinal; FLD_ERR_DEVICE if the runtime query fails. */
+fld_status fld_device_arch(int device, char *buf, int len);
 
 /* Batched solve: nvol volumes of sizes dims3[3v..3v+2] and edges h[v], each
  * with nchan colour channels that share the extinction field and have their

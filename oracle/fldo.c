@@ -955,7 +955,7 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
     H.lv[0].D = D;
     memcpy(H.lv[0].sa, sig_a, sizeof(double) * n);
     int it = 0, len = 0, status = FLDO_NOT_CONVERGED, first = 1;
-    double rel = NAN, gamma_prev = 0.0;
+    double rel = NAN, rel_prev = NAN, gamma_prev = 0.0;
     for (;;) {
         fldo_limiter_pass(p, phi, sig_hat, D);
         rel = fldo_residual(p, phi, D, sig_a, j_src, r) / p->jnorm;
@@ -980,14 +980,19 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
             for (long c = 0; c < n; ++c)
                 e[c] = e1[c] + e[c];
         double theta;
-        if (o->step_mode == 1) {
+        if (o->step_mode == 1 || o->step_mode == 2) {
             double gamma = 0.0, e_rprev = 0.0;
             for (long c = 0; c < n; ++c) {
                 gamma += r[c] * e[c];
                 e_rprev += e[c] * r_prev[c];
             }
+            /* Polak-Ribiere+ coefficient; mode 1 restarts (beta = 0) after an
+             * iteration that raised the residual norm by more than the factor
+             * restart_growth */
             double beta = 0.0;
-            if (it > 0) {
+            const int restart = o->step_mode == 1 && o->restart_growth > 0.0 &&
+                                rel > o->restart_growth * rel_prev;
+            if (it > 0 && !restart) {
                 beta = (gamma - e_rprev) / gamma_prev;
                 if (!(beta > 0.0))
                     beta = 0.0;
@@ -1002,6 +1007,7 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
             }
             theta = rp / pq;
             gamma_prev = gamma;
+            rel_prev = rel;
             memcpy(r_prev, r, sizeof(double) * n);
         } else {
             memcpy(dir, e, sizeof(double) * n);

@@ -50,8 +50,12 @@ typedef struct fldo_solve_opts {
     double tol;               /* stop when ||r||/||j|| <= tol */
     int check_every;          /* Alg. 1: iterations between residual checks */
     double theta;             /* multigrid correction step (step_mode 0) */
-    int step_mode;            /* 0: p = e, fixed theta; 1: nonlinear PCG direction and step */
+    int step_mode;            /* 0: p = e, fixed theta; 1: nonlinear PCG direction and step,
+                                 restarted after a residual increase; 2: the same without
+                                 restarts */
     double deflate_tau;       /* cluster threshold (x grid extent); <= 0 disables deflation */
+    double restart_growth;    /* step_mode 1: restart when rel_k > restart_growth * rel_{k-1};
+                                 <= 0 never restarts */
 } fldo_solve_opts;
 
 typedef struct fldo_result {

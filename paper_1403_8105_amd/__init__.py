@@ -36,7 +36,7 @@ class fld_options(C.Structure):
                 ("tol", C.c_double), ("check_every", C.c_int), ("device", C.c_int),
                 ("stream", C.c_void_p), ("timing", C.c_int), ("deflate_tau", C.c_double),
                 ("graph", C.c_int), ("task_cells0", C.c_int), ("coarse_blocks", C.c_int),
-                ("colour_split", C.c_int)]
+                ("colour_split", C.c_int), ("restart_growth", C.c_double)]
 
 
 class fld_report(C.Structure):
@@ -59,7 +59,7 @@ EXPORTS = ["fld_default_options", "fld_create", "fld_set_medium", "fld_set_mediu
            "fld_solve", "fld_solve_device", "fld_solve_resume", "fld_residual",
            "fld_residual_device", "fld_destroy", "fld_status_string", "fld_last_error",
            "fld_batch_create", "fld_batch_set_volume", "fld_batch_solve", "fld_batch_destroy",
-           "fld_batch_last_error"]
+           "fld_batch_last_error", "fld_device_arch"]
 
 
 def lib():
@@ -71,6 +71,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, ip = C.c_void_p, C.POINTER(C.c_int)
         L.fld_default_options.argtypes = [C.POINTER(fld_options)]
+        L.fld_device_arch.argtypes = [C.c_int, C.c_char_p, C.c_int]
         L.fld_create.argtypes = [C.POINTER(fld_options), C.c_int, C.c_int, C.c_int, C.c_double,
                                  C.POINTER(vp)]
         L.fld_set_medium.argtypes = [vp, vp, vp, vp]
@@ -222,6 +223,15 @@ def fld_residual_device(ctx, d_phi: int = 0, d_r_out: int = 0):
 
 def fld_destroy(ctx):
     lib().fld_destroy(ctx)
+
+
+def fld_device_arch(device: int = 0) -> str:
+    """GPU architecture name of a device, e.g. "gfx950"."""
+    buf = C.create_string_buffer(64)
+    s = lib().fld_device_arch(device, buf, 64)
+    if s != FLD_OK:
+        raise FldError(s, f"fld_device_arch({device})")
+    return buf.value.decode()
 
 
 def fld_status_string(s: int) -> str:

@@ -1,0 +1,164 @@
+"""Autotuner of the multigrid solve: launch shapes and smoothing schedule.
+
+Two phases, both timed on the GPU through the C ABI with the inputs resident
+in device memory:
+
+1. Launch shapes (``task_cells0``, ``coarse_blocks``).  They change no result
+   bit, so a short capped solve per candidate gives the time per outer
+   iteration; the fastest wins.
+2. Smoothing schedule (``nu1``, ``nu2``, ``omega_s``) and the growth
+   factor that restarts the conjugate-gradient direction
+   (``restart_growth``; restarts are never switched off).  These change the
+   iteration, so every candidate runs a full solve to the tolerance with the
+   phase-1 shape; the shortest time to tolerance wins.
+
+The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
+limiter), in ``tuned.json`` beside this file unless another path is given.
+``Solver``-level callers pass ``tuned_options(...)`` as keyword options.
+
+Command line (tunes the synthetic cloud workload of ``synth.media``)::
+
+    python -m paper_1403_8105_amd.autotune --workload cloud256 --precision mixed
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(HERE, "tuned.json")
+
+SHAPES = [(4096, 2048), (2048, 2048), (8192, 2048), (16384, 2048), (4096, 1024), (4096, 4096)]
+SCHEDULES = [(2, 2, 1.0), (1, 1, 1.0), (2, 1, 1.0), (1, 2, 1.0), (3, 3, 1.0), (2, 2, 1.15),
+             (3, 3, 1.15), (4, 4, 1.0)]
+GROWTHS = [2.0, 10.0]
+
+
+def cache_key(arch: str, shape, precision: str, limiter: str) -> str:
+    return f"{arch}|{shape[0]}x{shape[1]}x{shape[2]}|{precision}|{limiter}"
+
+
+def device_arch(device: int = 0) -> str:
+    import paper_1403_8105_amd as F
+
+    return F.fld_device_arch(device)
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def tuned_options(shape, precision: str = "mixed", limiter: str = "lp", arch: str | None = None,
+                  path: str = CACHE) -> dict:
+    """Cached options for this grid, or {} when it was never tuned."""
+    arch = arch or device_arch()
+    entry = load_cache(path).get(cache_key(arch, shape, precision, limiter))
+    return dict(entry["options"]) if entry else {}
+
+
+def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
+    """One device solve; returns (wall ms, report)."""
+    import torch
+
+    s = F.Solver(st.shape, h, stream=stream, **opts)
+    try:
+        s.set_medium_device(*dev_inputs, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = F.fld_solve_device(s.ctx, d_phi,
+                                 allow=(F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED))
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, rep
+    finally:
+        s.close()
+
+
+def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
+         probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print) -> dict:
+    """Tune one grid/medium; stores and returns the cache entry."""
+    import torch
+
+    import paper_1403_8105_amd as F
+
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (sigma_t, albedo, Q)]
+    d_phi = torch.empty_like(d[0])
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    ptrs = [t.data_ptr() for t in d]
+    base = dict(precision=precision, limiter=limiter)
+
+    # phase 1: launch shapes, time per outer iteration of a capped solve
+    shape_ms = {}
+    for tc0, cb in SHAPES:
+        o = dict(base, tol=0.0, max_iters=probe_iters, task_cells0=tc0, coarse_blocks=cb)
+        _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)      # warm
+        ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
+        shape_ms[(tc0, cb)] = ms / max(rep["iterations"], 1)
+        log(f"autotune: task_cells0={tc0} coarse_blocks={cb}: {shape_ms[(tc0, cb)]:.4f} ms/it")
+    tc0, cb = min(shape_ms, key=shape_ms.get)
+
+    # phase 2: smoothing schedules, full solves to tol
+    results = []
+    best = None
+    for nu1, nu2, ws in SCHEDULES:
+        for gr in GROWTHS:
+            o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
+                     nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr)
+            ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
+            ok = rep["status"] == F.FLD_OK
+            results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
+                            "ms": ms, "iterations": rep["iterations"], "rel": rep["rel"],
+                            "converged": ok})
+            log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr}: "
+                f"{rep['iterations']} its, rel {rep['rel']:.2e}, {ms:.0f} ms"
+                f"{'' if ok else ' (not converged)'}")
+            if ok and (best is None or ms < best["ms"]):
+                best = results[-1]
+    if best is None:
+        raise RuntimeError("autotune: no schedule reached the tolerance")
+    entry = {
+        "options": {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"],
+                    "nu2": best["nu2"], "omega_s": best["omega_s"],
+                    "restart_growth": best["restart_growth"]},
+        "tol": tol,
+        "ms_to_tol": best["ms"],
+        "iterations": best["iterations"],
+        "shape_ms_per_iteration": {f"{a},{b}": v for (a, b), v in shape_ms.items()},
+        "schedules": results,
+    }
+    if path:
+        arch = device_arch()
+        cache = load_cache(path)
+        cache[cache_key(arch, sigma_t.shape, precision, limiter)] = entry
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return entry
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", default="cloud256")
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--limiter", default="lp")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(HERE))
+    from synth import media
+
+    st, al, Q, h = media.config(args.workload, n=args.n)
+    entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
+                 path=args.out, log=lambda m: print(m, flush=True))
+    print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
+                      "iterations": entry["iterations"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -908,7 +908,7 @@ struct fld_engine_impl {
                          d_part[1], use_defl ? d_alpha : nullptr, kmode);
         launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
         launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
-        launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0);
+        launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0, opt.restart_growth);
         hipEvent_t td = tic();
         launch_npcg_dir(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
                         (k - 1) & 1, k & 1, d_part[2], d_part[3], kmode);
@@ -1160,6 +1160,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->task_cells0 < 512 || o->task_cells0 > 65536 || (o->task_cells0 & (o->task_cells0 - 1))) { err = "task_cells0 must be a power of two in [512,65536]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->coarse_blocks < 64 || o->coarse_blocks > 65536) { err = "coarse_blocks must lie in [64,65536]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->colour_split != 0 && o->colour_split != 1) { err = "colour_split must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!std::isfinite(o->restart_growth)) { err = "restart_growth must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1216,6 +1217,25 @@ void fill_report(fld_report *rep, fld_engine_impl &E, int p, int status, double 
 
 extern "C" {
 
+fld_status fld_device_arch(int device, char *buf, int len)
+{
+    if (!buf || len < 2 || device < 0)
+        return FLD_ERR_INVALID_ARGUMENT;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess)
+        return FLD_ERR_DEVICE;
+    if (device >= count)
+        return FLD_ERR_INVALID_ARGUMENT;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return FLD_ERR_DEVICE;
+    int k = 0;
+    for (; k + 1 < len && prop.gcnArchName[k] && prop.gcnArchName[k] != ':'; ++k)
+        buf[k] = prop.gcnArchName[k];
+    buf[k] = 0;
+    return FLD_OK;
+}
+
 fld_status fld_default_options(fld_options *o)
 {
     if (!o)
@@ -1246,6 +1266,7 @@ fld_status fld_default_options(fld_options *o)
     o->task_cells0 = 4096;
     o->coarse_blocks = 2048;
     o->colour_split = 1;
+    o->restart_growth = 2.0;
     return FLD_OK;
 }
 

@@ -76,7 +76,7 @@ struct CTask {
 // Per-problem device scalars.
 enum Scalar {
     S_JN2 = 0, S_JBAR, S_JNORM, S_RES2, S_REL, S_GAMMA, S_GAMMA_PREV, S_SIGMA, S_RP, S_PAP,
-    S_BETA, S_THETA, S_SWEEP2, S_AUX, S_COUNT
+    S_BETA, S_THETA, S_SWEEP2, S_AUX, S_REL_PREV, S_COUNT
 };
 
 enum Limiter { L_CDA = 0, L_LP = 1, L_SUM = 2, L_MAX = 3, L_KERSHAW = 4, L_LARSEN = 5 };
@@ -110,7 +110,8 @@ void launch_rel(hipStream_t s, int nprob, double *scal, const int *active);
 void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const int *active, int b0_idx, double *pg, double *ps,
                       const double *alpha, int mixed);
-void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first);
+void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first,
+                      double restart_growth);
 void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                      const int *active, const double *scal, int b0_idx, int pin, int pout,
                      double *prp, double *ppap, int mixed);

@@ -386,7 +386,9 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
                 }
                 if (use_dir && dst != src)
                     st4(phi_out + c0, P.c);
-#pragma unroll
+                // one cell at a time: unrolling the four limiter evaluations
+                // raises the register footprint and halves the occupancy
+#pragma unroll 1
                 for (int m = 0; m < 4; ++m) {
                     Dq[m] = limiter(f.limiter, Rq[m], f.larsen_n) / sh[m];
                     D32q[m] = (float)Dq[m];
@@ -1079,20 +1081,25 @@ __global__ void k_rel(int nprob, double *scal, const int *active)
     s[S_REL] = sqrt(s[S_RES2]) / s[S_JNORM];
 }
 
-__global__ void k_npcg_beta(int nprob, double *scal, const int *active, int first)
+// Polak-Ribiere+ coefficient of the conjugate-gradient step, restarted
+// (beta = 0) at the first iteration and after an iteration that raised the
+// residual norm by more than the factor `growth` (<= 0: no restarts).
+__global__ void k_npcg_beta(int nprob, double *scal, const int *active, int first, double growth)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob || (active && !active[p]))
         return;
     double *s = scal + p * S_COUNT;
     double beta = 0.0;
-    if (!first) {
+    const bool restart = growth > 0.0 && s[S_REL] > growth * s[S_REL_PREV];
+    if (!first && !restart) {
         beta = (s[S_GAMMA] - s[S_SIGMA]) / s[S_GAMMA_PREV];
         if (!(beta > 0.0))
             beta = 0.0;
     }
     s[S_BETA] = beta;
     s[S_GAMMA_PREV] = s[S_GAMMA];
+    s[S_REL_PREV] = s[S_REL];
 }
 
 __global__ void k_npcg_theta(int nprob, double *scal, const int *active)
@@ -1898,10 +1905,11 @@ void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int 
                            tasks, ntasks, active, b0_idx, alpha);
 }
 
-void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first)
+void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first,
+                      double restart_growth)
 {
     hipLaunchKernelGGL(k_npcg_beta, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, active,
-                       first);
+                       first, restart_growth);
 }
 
 void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,

@@ -304,3 +304,44 @@ def test_batch_mixing_split_and_natural_volumes():
             assert iters[r] == rep1["iterations"] == 7
             np.testing.assert_array_equal(outs[r], phi)
             r += 1
+
+
+@pytest.mark.parametrize("nu1,nu2,omega_s", [(1, 1, 1.0), (2, 1, 1.0), (1, 2, 1.0), (3, 3, 1.0),
+                                             (2, 2, 1.15)])
+def test_mg_schedules_iterate_parity(nu1, nu2, omega_s):
+    # every smoothing schedule the autotuner may pick follows the oracle
+    st, al, Q, h = media.config("cloud256", n=32)
+    prob = oracle.setup(st, al, Q, h)
+    kw = dict(nu1=nu1, nu2=nu2, omega_s=omega_s)
+    for k in (1, 3, 10):
+        ref = oracle.solve(prob, method="mg", tol=0.0, max_iters=k, **kw)
+        s = gpu_solver(st.shape, h, st, al, Q, tol=0.0, max_iters=k, **kw)
+        phi, rep = s.solve()
+        np.testing.assert_allclose(rep["history"], ref.history, rtol=1e-9)
+        assert rel_l2(phi, ref.phi) <= 1e-10, k
+    # and the mixed form still converges with it
+    s = gpu_solver(st.shape, h, st, al, Q, precision="mixed", tol=1e-6, max_iters=1000, **kw)
+    _, rep = s.solve()
+    assert rep["status"] == F.FLD_OK
+
+
+def test_full_size_256_in_the_bench_configuration():
+    # the bench's grid and options: FP64 multigrid iterates follow the oracle,
+    # and the mixed solve's fluence has, per the oracle, the residual it reports
+    from paper_1403_8105_amd.autotune import tuned_options
+
+    st, al, Q, h = media.config("cloud256")
+    prob = oracle.setup(st, al, Q, h)
+    ref = oracle.solve(prob, method="mg", tol=0.0, max_iters=2)
+    s = gpu_solver(st.shape, h, st, al, Q, tol=0.0, max_iters=2)
+    phi, rep = s.solve()
+    s.close()
+    np.testing.assert_allclose(rep["history"], ref.history, rtol=1e-9)
+    assert rel_l2(phi, ref.phi) <= 1e-10
+    opts = tuned_options(st.shape, "mixed", "lp")
+    s = gpu_solver(st.shape, h, st, al, Q, precision="mixed", tol=1e-6, max_iters=5000, **opts)
+    phi, rep = s.solve()
+    s.close()
+    assert rep["status"] == F.FLD_OK and rep["rel"] <= 1e-6
+    _, rel_o, _ = oracle.nonlinear_residual(prob, phi)
+    assert rel_o == pytest.approx(rep["rel"], rel=1e-9)
