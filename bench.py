@@ -122,8 +122,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default="mixed")
-    ap.add_argument("--max-iters", type=int, default=5000,
-                    help="outer iteration cap (short counter runs only)")
+    ap.add_argument("--max-iters", type=int, default=None,
+                    help="outer iteration cap (default 5000; 20000 for cloud512)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the plain FP64 GPU solve reported beside the mixed one")
@@ -146,6 +146,7 @@ def main():
         copy_calibration(args.copy_bytes)
         return
     if args.workload == "batch":
+        args.max_iters = args.max_iters or 5000
         run_batch(args)
         return
     if args.workload == "cloud128-fp64":
@@ -155,9 +156,10 @@ def main():
         args.n, cfg = 512, "cloud512"
         args.no_fp64 = args.no_cpu_baseline = True
         args.chunk = args.chunk or 1000
-        args.max_iters = max(args.max_iters, 20000)
+        args.max_iters = args.max_iters or 20000
     else:
         cfg = "cloud256"
+    args.max_iters = args.max_iters or 5000
 
     import torch
     import paper_1403_8105_amd as F
@@ -179,10 +181,17 @@ def main():
 
     from paper_1403_8105_amd.autotune import tuned_options
 
-    tuned = {}
+    tuned, tuned_from = {}, {}
     for prec in ("mixed", "fp64"):
-        tuned[prec] = {} if args.no_tuned else tuned_options(st.shape, prec, "lp")
-        log(f"bench: {prec} options from the autotuner cache: {tuned[prec] or 'none (defaults)'}")
+        tuned[prec], tuned_from[prec] = {}, None
+        if not args.no_tuned:
+            # only the grid's own entry: a schedule tuned on 256^3 (omega_s
+            # 1.15, restart factor 10) diverges on the 512^3 cloud
+            tuned[prec] = tuned_options(st.shape, prec, "lp")
+            if tuned[prec]:
+                tuned_from[prec] = "x".join(map(str, st.shape))
+        log(f"bench: {prec} options from the autotuner cache ({tuned_from[prec]}): "
+            f"{tuned[prec] or 'none (defaults)'}")
 
     def make(precision, timing):
         s = F.Solver(st.shape, h, precision=precision, tol=args.tol,
@@ -269,7 +278,8 @@ def main():
                                f"V({tuned[args.precision].get('nu1', 2)},"
                                f"{tuned[args.precision].get('nu2', 2)}) to rel {args.tol:g}",
                    "grid": [n, n, n], "tol": args.tol, "precision": args.precision,
-                   "tuned_options": tuned[args.precision]},
+                   "tuned_options": tuned[args.precision],
+                   "tuned_on_grid": tuned_from[args.precision]},
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg,
@@ -299,7 +309,6 @@ def run_batch(args):
     """16 volumes x 3 colour channels in one batched solve (one JSON line)."""
     import torch
     import paper_1403_8105_amd as F
-    from paper_1403_8105_amd.autotune import tuned_options
     from synth import media
 
     log("bench: generating the 16-volume batch")
@@ -307,8 +316,8 @@ def run_batch(args):
     dims = [(v["n"],) * 3 for v in vols]
     shapes = [d for d in dims for _ in range(3)]
     voxels = sum(a * b * c for a, b, c in dims)
-    # launch shapes and schedule of the 256^3 tuning (the batch has no entry of its own)
-    tuned = {} if args.no_tuned else tuned_options((256, 256, 256), "mixed", "lp")
+    # the batch has no tuner entry of its own: default launch shapes and schedule
+    tuned = {}
     o = F.fld_default_options(precision="mixed", tol=1e-6, max_iters=args.max_iters, **tuned)
     b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
     for q, v in enumerate(vols):

@@ -786,14 +786,15 @@ struct fld_engine_impl {
 
     // One finest-level half-sweep must move, per cell of the grid, the other
     // colour's e (half), all of D, this colour's b and sa (half each) and its
-    // new e (half): 3 values of precision T.
+    // new e (half): 3 values of precision T; with over-relaxation (omega_s !=
+    // 1) also this colour's old e (half).
     template <typename T>
     void smooth(Grid *G, int l, int colour)
     {
         hipEvent_t a = l == 0 ? tic() : nullptr;
         launch_smooth<T>(stream, G, mid[l].d, mid[l].n, d_active, colour, opt.omega_s, l == 0);
         if (l == 0)
-            toc(a, 0, 3.0 * sizeof(T));
+            toc(a, 0, (opt.omega_s != 1.0 ? 3.5 : 3.0) * sizeof(T));
     }
 
     double active_fine_cells() const

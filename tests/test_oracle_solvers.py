@@ -241,3 +241,18 @@ def test_deflation_keeps_the_fixed_point(oracle_mod):
     assert a.status == b.status == "converged"
     assert b.iterations < a.iterations / 2          # the point of deflating
     assert np.linalg.norm(a.phi - b.phi) <= 1e-9 * np.linalg.norm(a.phi)
+
+
+def test_direction_restarts_keep_the_fixed_point(oracle_mod):
+    # restarting the conjugate direction changes the path, not the solution;
+    # a growth factor of 1 restarts after every increase of the residual
+    st, al, Q, h = media.config("cloud256", n=32)
+    prob = oracle_mod.setup(st, al, Q, h)
+    runs = [oracle_mod.solve(prob, method="mg", tol=1e-11, max_iters=3000, restart_growth=g)
+            for g in (0.0, 1.0, 2.0)]
+    assert all(r.status == "converged" for r in runs)
+    for r in runs[1:]:
+        assert np.linalg.norm(r.phi - runs[0].phi) <= 1e-9 * np.linalg.norm(runs[0].phi)
+    # the restart rule is active: with factor 1 the path differs from no restarts
+    assert runs[1].iterations != runs[0].iterations or \
+        not np.array_equal(runs[1].history, runs[0].history)
