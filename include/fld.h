@@ -116,6 +116,8 @@ typedef struct fld_options {
     double restart_growth;/* multigrid: the conjugate-gradient direction restarts (beta = 0)
                              after an outer iteration that raised ||r|| by more than this
                              factor; <= 0 never restarts (default 2)                       */
+    double corr_scale;    /* multigrid: factor on the coarse-grid correction of the finest
+                             level (piecewise-constant prolongation under-corrects; default 1) */
 } fld_options;
 
 typedef struct fld_report {

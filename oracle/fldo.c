@@ -508,14 +508,14 @@ static void galerkin_faces(const mg_level *F, mg_level *C, double d_ghost, int m
 }
 
 /* e_fine += P e_coarse: every fine cell receives its parent's value. */
-static void prolong_add(const mg_level *C, mg_level *F)
+static void prolong_add(const mg_level *C, mg_level *F, double scale)
 {
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < F->nx; ++i)
         for (int j = 0; j < F->ny; ++j)
             for (int k = 0; k < F->nz; ++k) {
                 long c = idx3(F->ny, F->nz, i, j, k);
-                F->e[c] = F->e[c] + C->e[idx3(C->ny, C->nz, i / 2, j / 2, k / 2)];
+                F->e[c] = F->e[c] + scale * C->e[idx3(C->ny, C->nz, i / 2, j / 2, k / 2)];
             }
 }
 
@@ -604,7 +604,7 @@ static void vcycle(mg_level *lv, int l, int nlev, const fldo_solve_opts *o, doub
     level_residual(L, d_ghost, mirror, L->r);
     mean8(lv[l + 1].nx, lv[l + 1].ny, lv[l + 1].nz, L->ny, L->nz, L->r, lv[l + 1].b);
     vcycle(lv, l + 1, nlev, o, d_ghost, mirror, chol);
-    prolong_add(&lv[l + 1], L);
+    prolong_add(&lv[l + 1], L, l == 0 ? o->corr_scale : 1.0);
     for (int s = 0; s < o->nu2; ++s) {
         level_smooth_colour(L, d_ghost, mirror, 1, o->omega_s);
         level_smooth_colour(L, d_ghost, mirror, 0, o->omega_s);

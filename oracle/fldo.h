@@ -56,6 +56,7 @@ typedef struct fldo_solve_opts {
     double deflate_tau;       /* cluster threshold (x grid extent); <= 0 disables deflation */
     double restart_growth;    /* step_mode 1: restart when rel_k > restart_growth * rel_{k-1};
                                  <= 0 never restarts */
+    double corr_scale;        /* factor on the prolongated coarse-grid correction */
 } fldo_solve_opts;
 
 typedef struct fldo_result {

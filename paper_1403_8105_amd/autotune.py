@@ -8,9 +8,11 @@ in device memory:
    iteration; the fastest wins.
 2. Smoothing schedule (``nu1``, ``nu2``, ``omega_s``) and the growth
    factor that restarts the conjugate-gradient direction
-   (``restart_growth``; restarts are never switched off).  These change the
-   iteration, so every candidate runs a full solve to the tolerance with the
-   phase-1 shape; the shortest time to tolerance wins.
+   (``restart_growth``; restarts are never switched off), then the factor on
+   the finest coarse-grid correction (``corr_scale``) for the winner.  These
+   change the iteration, so every candidate runs a full solve to the
+   tolerance with the phase-1 shape; the shortest time to tolerance wins.
+   ``quick`` keeps the default schedule and tunes only ``corr_scale``.
 
 The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
 limiter), in ``tuned.json`` beside this file unless another path is given.
@@ -35,6 +37,8 @@ SHAPES = [(4096, 2048), (2048, 2048), (8192, 2048), (16384, 2048), (4096, 1024),
 SCHEDULES = [(2, 2, 1.0), (1, 1, 1.0), (2, 1, 1.0), (1, 2, 1.0), (3, 3, 1.0), (2, 2, 1.15),
              (3, 3, 1.15), (4, 4, 1.0)]
 GROWTHS = [2.0, 10.0]
+SCALES = [1.0, 1.2, 1.4, 1.6, 1.8]
+DEFAULT_SCHEDULE = (2, 2, 1.0, 2.0)
 
 
 def cache_key(arch: str, shape, precision: str, limiter: str) -> str:
@@ -80,7 +84,8 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 
 
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
-         probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print) -> dict:
+         probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
+         quick: bool = False) -> dict:
     """Tune one grid/medium; stores and returns the cache entry."""
     import torch
 
@@ -103,29 +108,42 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         log(f"autotune: task_cells0={tc0} coarse_blocks={cb}: {shape_ms[(tc0, cb)]:.4f} ms/it")
     tc0, cb = min(shape_ms, key=shape_ms.get)
 
-    # phase 2: smoothing schedules, full solves to tol
+    # phase 2: schedules and restart factors, then the correction factor;
+    # full solves to tol
     results = []
+
+    def run(nu1, nu2, ws, gr, sc):
+        o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
+                 nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc)
+        ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
+        ok = rep["status"] == F.FLD_OK
+        results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
+                        "corr_scale": sc, "ms": ms, "iterations": rep["iterations"],
+                        "rel": rep["rel"], "converged": ok})
+        log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} corr_scale={sc}: "
+            f"{rep['iterations']} its, rel {rep['rel']:.2e}, {ms:.0f} ms"
+            f"{'' if ok else ' (not converged)'}")
+        return results[-1] if ok else None
+
+    def better(a, b):
+        return a if b is None or (a is not None and a["ms"] < b["ms"]) else b
+
     best = None
-    for nu1, nu2, ws in SCHEDULES:
-        for gr in GROWTHS:
-            o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
-                     nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr)
-            ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
-            ok = rep["status"] == F.FLD_OK
-            results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                            "ms": ms, "iterations": rep["iterations"], "rel": rep["rel"],
-                            "converged": ok})
-            log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr}: "
-                f"{rep['iterations']} its, rel {rep['rel']:.2e}, {ms:.0f} ms"
-                f"{'' if ok else ' (not converged)'}")
-            if ok and (best is None or ms < best["ms"]):
-                best = results[-1]
+    if quick:
+        best = run(*DEFAULT_SCHEDULE, 1.0)
+    else:
+        for nu1, nu2, ws in SCHEDULES:
+            for gr in GROWTHS:
+                best = better(run(nu1, nu2, ws, gr, 1.0), best)
     if best is None:
         raise RuntimeError("autotune: no schedule reached the tolerance")
+    for sc in SCALES[1:]:
+        best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"], sc),
+                      best)
     entry = {
         "options": {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"],
                     "nu2": best["nu2"], "omega_s": best["omega_s"],
-                    "restart_growth": best["restart_growth"]},
+                    "restart_growth": best["restart_growth"], "corr_scale": best["corr_scale"]},
         "tol": tol,
         "ms_to_tol": best["ms"],
         "iterations": best["iterations"],
@@ -149,13 +167,17 @@ def main(argv=None):
     ap.add_argument("--limiter", default="lp")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--out", default=CACHE)
+    ap.add_argument("--quick", action="store_true",
+                    help="default schedule; tune launch shapes and corr_scale only")
+    ap.add_argument("--max-iters", type=int, default=5000)
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from synth import media
 
     st, al, Q, h = media.config(args.workload, n=args.n)
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
-                 path=args.out, log=lambda m: print(m, flush=True))
+                 path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
+                 max_iters=args.max_iters)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"]}), flush=True)
 

@@ -826,7 +826,8 @@ struct fld_engine_impl {
         for (int l = max_levels - 2; l >= 0; --l) {
             if (!mid[l].n)
                 continue;
-            launch_prolong<T>(stream, G, mid[l].d, mid[l].n, d_active, lsp);
+            launch_prolong<T>(stream, G, mid[l].d, mid[l].n, d_active, lsp,
+                              l == 0 ? opt.corr_scale : 1.0);
             for (int s = 0; s < opt.nu2; ++s) {
                 smooth<T>(G, l, 1);
                 smooth<T>(G, l, 0);
@@ -1162,6 +1163,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->coarse_blocks < 64 || o->coarse_blocks > 65536) { err = "coarse_blocks must lie in [64,65536]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->colour_split != 0 && o->colour_split != 1) { err = "colour_split must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!std::isfinite(o->restart_growth)) { err = "restart_growth must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->corr_scale > 0.0 && o->corr_scale <= 4.0)) { err = "corr_scale must lie in (0,4]"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1268,6 +1270,7 @@ fld_status fld_default_options(fld_options *o)
     o->coarse_blocks = 2048;
     o->colour_split = 1;
     o->restart_growth = 2.0;
+    o->corr_scale = 1.0;
     return FLD_OK;
 }
 

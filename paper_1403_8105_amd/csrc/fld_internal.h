@@ -143,7 +143,7 @@ void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int nt
                      const int *active, int sp);
 template <typename T>
 void launch_prolong(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                    const int *active, int sp);
+                    const int *active, int sp, double scale);
 template <typename T>
 void launch_galerkin(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
                      const int *active, int sp);

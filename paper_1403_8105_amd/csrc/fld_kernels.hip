@@ -1555,11 +1555,13 @@ k_restrict(const Grid *grids, const Task *tasks, int ntasks, const int *active)
     }
 }
 
-// e_fine += e_coarse(parent).  Tasks run over the cells of the fine grid.
+// e_fine += scale * e_coarse(parent).  Tasks run over the cells of the fine
+// grid; scale != 1 only for the correction of the finest level.
 template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
-k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
+k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active, double scale)
 {
+    const T s = (T)scale;
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Grid &F = grids[tk.grid];
@@ -1575,7 +1577,7 @@ k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active)
             int i, j, k;
             dec(c, i, j, k);
             const long long o = sp ? sidx(c, (i + j + k) & 1) : c;
-            ef[o] = ef[o] + ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
+            ef[o] = ef[o] + s * ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
         }
     }
 }
@@ -1958,10 +1960,10 @@ void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int nt
 
 template <typename T>
 void launch_prolong(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
-                    const int *active, int sp)
+                    const int *active, int sp, double scale)
 {
     hipLaunchKernelGGL(FLD_PICK_SP(k_prolong, T, sp), dim3(grid_for(ntasks)), dim3(kBlock), 0, s,
-                       grids, tasks, ntasks, active);
+                       grids, tasks, ntasks, active, scale);
 }
 
 template <typename T>
@@ -1995,7 +1997,8 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
     template void launch_smooth<T>(hipStream_t, const Grid *, const Task *, int, const int *,    \
                                    int, double, bool);                                           \
     template void launch_restrict<T>(hipStream_t, const Grid *, const Task *, int, const int *, int); \
-    template void launch_prolong<T>(hipStream_t, const Grid *, const Task *, int, const int *, int);  \
+    template void launch_prolong<T>(hipStream_t, const Grid *, const Task *, int, const int *, int,  \
+                                    double);  \
     template void launch_galerkin<T>(hipStream_t, const Grid *, const Task *, int, const int *, int); \
     template void launch_mean8_sa<T>(hipStream_t, const Grid *, const Task *, int);              \
     template void launch_coarse_solve<T>(hipStream_t, const Grid *, const int *, int,            \
