@@ -82,6 +82,8 @@ def lib():
                                     C.POINTER(C.c_int)]
         L.fldo_solve.argtypes = [P(Params), P(SolveOpts), _dp, _dp, _dp, _dp, _dp, _dp, C.c_int,
                                  P(Result)]
+        L.fldo_light_bake.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp,
+                                      _dp]
         _lib = L
     return _lib
 
@@ -277,6 +279,17 @@ def cholesky(M):
     if lib().fldo_cholesky_factor(n, _ptr(Lf)) != 0:
         raise np.linalg.LinAlgError("not positive definite")
     return np.tril(Lf)
+
+
+def light_bake(sigma_t, albedo, h, light=1.0):
+    """Single-scatter source q = L sigma_s T of a directional light travelling
+    +z (Sec. 3 deep shadow map; midpoint transmittance, reading A17)."""
+    st = _f64(sigma_t)
+    al = _f64(np.broadcast_to(albedo, st.shape))
+    q = np.empty_like(st)
+    nx, ny, nz = st.shape
+    lib().fldo_light_bake(nx, ny, nz, float(h), float(light), _ptr(st), _ptr(al), _ptr(q))
+    return q
 
 
 def cholesky_solve(M, rhs):

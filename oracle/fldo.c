@@ -1063,3 +1063,29 @@ int fldo_solve(const fldo_params *p, const fldo_solve_opts *o, const double *sig
         return solve_alg1(p, o, sig_hat, sig_a, j_src, phi, D, hist, cap, res);
     return solve_mg(p, o, sig_hat, sig_a, j_src, phi, hist, cap, res);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Light baking (Sec. 3: single-scatter source of an external directional    */
+/* light, q_ri = L_l sigma_s T with T the transmittance towards the light,   */
+/* the "deep shadow map"; Sec. 6 bakes it by ray-marching).  Reading: the     */
+/* light travels +z and enters at the z = 0 face; in voxel k of a column     */
+/* T = exp(-h (sum_{k' < k} sigma_t + sigma_t(k)/2)) (midpoint of the voxel,  */
+/* raw sigma_t), sigma_s = albedo sigma_t.  Pinned against the closed form of */
+/* a homogeneous column and the product form of T.                           */
+/* ------------------------------------------------------------------------ */
+void fldo_light_bake(int nx, int ny, int nz, double h, double light, const double *sigma_t,
+                     const double *albedo, double *q)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double tau = 0.0;                    /* sum of sigma_t over k' < k */
+            for (int k = 0; k < nz; ++k) {
+                long c = idx3(ny, nz, i, j, k);
+                double s = sigma_t[c];
+                double T = exp(-h * (tau + 0.5 * s));
+                q[c] = light * albedo[c] * s * T;
+                tau = tau + s;
+            }
+        }
+}

@@ -97,4 +97,8 @@ int fldo_solve(const fldo_params *p, const fldo_solve_opts *o, const double *sig
                const double *sig_a, const double *j_src, double *phi, double *D, double *hist,
                int cap, fldo_result *res);
 
+/* Single-scatter source of a directional light along +z (see fldo.c). */
+void fldo_light_bake(int nx, int ny, int nz, double h, double light, const double *sigma_t,
+                     const double *albedo, double *q);
+
 #endif
