@@ -208,6 +208,22 @@ const char *fld_last_error(const fld_context *c);
  * ordinal; FLD_ERR_DEVICE if the runtime query fails. */
 fld_status fld_device_arch(int device, char *buf, int len);
 
+/* Light baking: the single-scatter source of an external directional light,
+ * q_ri = L_l sigma_s T, T the transmittance from the voxel towards the light
+ * (the "deep shadow map" of Sec. 3; the paper bakes it by ray-marching,
+ * Sec. 6).  The light of radiance `light` travels +z and enters every column
+ * at its z = 0 face; in voxel k of a column
+ *     T = exp(-h (sum_{k' < k} sigma_t + sigma_t(k)/2))
+ * (midpoint of the voxel, raw sigma_t) and sigma_s = albedo * sigma_t.
+ * d_sigma_t, d_albedo (per voxel) and d_q are device arrays of nx*ny*nz
+ * float64 values, z fastest, owned by the caller; d_q must not alias the
+ * inputs.  The work is enqueued on hip_stream (NULL: the null stream) and the
+ * call returns without waiting.  FLD_ERR_INVALID_ARGUMENT for a NULL
+ * pointer, a size < 1, h <= 0, a negative light or non-finite values of
+ * either; FLD_ERR_DEVICE if the launch fails.  No context is needed. */
+fld_status fld_light_bake(const double *d_sigma_t, const double *d_albedo, double light, int nx,
+                          int ny, int nz, double h, double *d_q, void *hip_stream);
+
 /* Batched solve: nvol volumes of sizes dims3[3v..3v+2] and edges h[v], each
  * with nchan colour channels that share the extinction field and have their
  * own albedo and emission (the per-channel albedo pattern of Sec. 6).  All

@@ -60,7 +60,7 @@ EXPORTS = ["fld_default_options", "fld_create", "fld_set_medium", "fld_set_mediu
            "fld_solve", "fld_solve_device", "fld_solve_resume", "fld_residual",
            "fld_residual_device", "fld_destroy", "fld_status_string", "fld_last_error",
            "fld_batch_create", "fld_batch_set_volume", "fld_batch_solve", "fld_batch_destroy",
-           "fld_batch_last_error", "fld_device_arch"]
+           "fld_batch_last_error", "fld_device_arch", "fld_light_bake"]
 
 
 def lib():
@@ -73,6 +73,8 @@ def lib():
         vp, ip = C.c_void_p, C.POINTER(C.c_int)
         L.fld_default_options.argtypes = [C.POINTER(fld_options)]
         L.fld_device_arch.argtypes = [C.c_int, C.c_char_p, C.c_int]
+        L.fld_light_bake.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
+                                     vp, vp]
         L.fld_create.argtypes = [C.POINTER(fld_options), C.c_int, C.c_int, C.c_int, C.c_double,
                                  C.POINTER(vp)]
         L.fld_set_medium.argtypes = [vp, vp, vp, vp]
@@ -233,6 +235,16 @@ def fld_device_arch(device: int = 0) -> str:
     if s != FLD_OK:
         raise FldError(s, f"fld_device_arch({device})")
     return buf.value.decode()
+
+
+def fld_light_bake(d_sigma_t: int, d_albedo: int, light: float, shape, h: float, d_q: int,
+                   stream: int = 0):
+    """Bake q = light * albedo * sigma_t * T on the device (light along +z)."""
+    nx, ny, nz = shape
+    s = lib().fld_light_bake(d_sigma_t or None, d_albedo or None, float(light), nx, ny, nz,
+                             float(h), d_q or None, stream or None)
+    if s != FLD_OK:
+        raise FldError(s, "fld_light_bake")
 
 
 def fld_status_string(s: int) -> str:

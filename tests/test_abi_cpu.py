@@ -69,3 +69,13 @@ def test_null_handles():
     lib.fld_destroy(None)
     lib.fld_batch_destroy(None)
     assert F.fld_status_string(F.FLD_ERR_STATE) == "invalid call order"
+
+
+def test_light_bake_rejects_invalid_arguments():
+    import paper_1403_8105_amd as F
+
+    L = F.lib()
+    assert L.fld_light_bake(None, None, 1.0, 4, 4, 4, 0.25, None, None) == F.FLD_ERR_INVALID_ARGUMENT
+    assert L.fld_light_bake(1, 1, 1.0, 0, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
+    assert L.fld_light_bake(1, 1, -1.0, 4, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
+    assert L.fld_light_bake(1, 1, 1.0, 4, 4, 4, float("nan"), 1, None) == F.FLD_ERR_INVALID_ARGUMENT
