@@ -84,6 +84,8 @@ def lib():
                                  P(Result)]
         L.fldo_light_bake.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp,
                                       _dp]
+        L.fldo_render.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp,
+                                  _dp, _dp]
         _lib = L
     return _lib
 
@@ -290,6 +292,19 @@ def light_bake(sigma_t, albedo, h, light=1.0):
     nx, ny, nz = st.shape
     lib().fldo_light_bake(nx, ny, nz, float(h), float(light), _ptr(st), _ptr(al), _ptr(q))
     return q
+
+
+def render(sigma_t, albedo, src, phi, h, background=0.0):
+    """Primary ray-march image (nx, ny) of an orthographic camera along +z
+    (Sec. 3 primary ray-march; source 4 pi Q = src + sigma_s phi)."""
+    st = _f64(sigma_t)
+    al = _f64(np.broadcast_to(albedo, st.shape))
+    sr, ph = _f64(src), _f64(phi)
+    nx, ny, nz = st.shape
+    img = np.empty((nx, ny))
+    lib().fldo_render(nx, ny, nz, float(h), float(background), _ptr(st), _ptr(al), _ptr(sr),
+                      _ptr(ph), _ptr(img))
+    return img
 
 
 def cholesky_solve(M, rhs):

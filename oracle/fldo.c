@@ -1089,3 +1089,37 @@ void fldo_light_bake(int nx, int ny, int nz, double h, double light, const doubl
             }
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Primary ray-march (Sec. 3): the radiance reaching the camera is the        */
+/* attenuated back-light plus the source of every sample attenuated by the    */
+/* transmittance between the sample and the ray's end, Delta x times the sum; */
+/* with the diffusion solution the source is 4 pi Q = q_ri + sigma_s phi + j  */
+/* (Sec. 3, the source in terms of phi).  Reading: an orthographic camera on  */
+/* the +z side, one ray per (i, j) column travelling +z from the z = 0 face;  */
+/* the sample of voxel k sees T = exp(-h (sigma_t(k)/2 + sum_{k' > k}         */
+/* sigma_t)) (midpoint, as the bake), the back-light `background` enters at    */
+/* z = 0 and is attenuated by exp(-h sum_k sigma_t).  src = q_ri + j (the     */
+/* solver's emission), sigma_s = albedo sigma_t.  image: nx*ny, index i*ny+j. */
+/* Pinned against the closed form of a homogeneous column.                    */
+/* ------------------------------------------------------------------------ */
+void fldo_render(int nx, int ny, int nz, double h, double background, const double *sigma_t,
+                 const double *albedo, const double *src, const double *phi, double *image)
+{
+    const double four_pi = 4.0 * 3.14159265358979323846;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j) {
+            double tau = 0.0;                    /* sum of sigma_t over k' > k */
+            double radiance = 0.0;
+            for (int k = nz - 1; k >= 0; --k) {
+                long c = idx3(ny, nz, i, j, k);
+                double s = sigma_t[c];
+                double T = exp(-h * (0.5 * s + tau));
+                double Q = (src[c] + albedo[c] * s * phi[c]) / four_pi;
+                radiance = radiance + h * T * Q;
+                tau = tau + s;
+            }
+            image[(long)i * ny + j] = radiance + background * exp(-h * tau);
+        }
+}

@@ -101,4 +101,8 @@ int fldo_solve(const fldo_params *p, const fldo_solve_opts *o, const double *sig
 void fldo_light_bake(int nx, int ny, int nz, double h, double light, const double *sigma_t,
                      const double *albedo, double *q);
 
+/* Primary ray-march of an orthographic camera along +z (see fldo.c). */
+void fldo_render(int nx, int ny, int nz, double h, double background, const double *sigma_t,
+                 const double *albedo, const double *src, const double *phi, double *image);
+
 #endif

@@ -50,3 +50,39 @@ def test_uses_extinction_not_scattering_for_the_shadow(oracle_mod):
     qa = oracle_mod.light_bake(st, 1.0, 0.25)
     qb = oracle_mod.light_bake(st, 0.25, 0.25)
     np.testing.assert_allclose(qb, 0.25 * qa, rtol=1e-15)
+
+
+def test_render_homogeneous_column_closed_form(oracle_mod):
+    # constant sigma, albedo, src and phi: the sum is a geometric series
+    n, h, sig, alb, src, phi, bg = 24, 0.125, 3.0, 0.7, 2.0, 5.0, 0.6
+    shape = (2, 3, n)
+    img = oracle_mod.render(np.full(shape, sig), alb, np.full(shape, src), np.full(shape, phi), h,
+                            background=bg)
+    Q = (src + alb * sig * phi) / (4.0 * np.pi)
+    a = np.exp(-sig * h)
+    series = np.exp(-0.5 * sig * h) * (1.0 - a ** n) / (1.0 - a)     # sum_k exp(-sig h (k + 1/2))
+    want = bg * a ** n + h * Q * series
+    np.testing.assert_allclose(img, want, rtol=1e-13)
+
+
+def test_render_vacuum_and_order(oracle_mod):
+    rng = np.random.default_rng(8)
+    shape, h = (3, 2, 10), 0.1
+    st = np.zeros(shape)
+    src = rng.uniform(0.0, 1.0, shape)
+    phi = rng.uniform(0.0, 1.0, shape)
+    # vacuum: nothing attenuates and nothing scatters; the image is bg + h sum src / 4 pi
+    img = oracle_mod.render(st, 0.9, src, phi, h, background=0.25)
+    np.testing.assert_allclose(img, 0.25 + h * src.sum(axis=2) / (4 * np.pi), rtol=1e-14)
+    # an absorbing voxel in front of (z above) a source hides it; behind it, it does not
+    st = np.zeros((1, 1, 6))
+    src = np.zeros((1, 1, 6))
+    src[0, 0, 1] = 1.0
+    front = st.copy()
+    front[0, 0, 4] = 50.0
+    behind = st.copy()
+    behind[0, 0, 0] = 50.0
+    z = np.zeros_like(st)
+    i_front = oracle_mod.render(front, 0.0, src, z, 1.0)
+    i_behind = oracle_mod.render(behind, 0.0, src, z, 1.0)
+    assert i_front[0, 0] < 1e-20 and i_behind[0, 0] == pytest.approx(1.0 / (4 * np.pi), rel=1e-15)
