@@ -29,7 +29,9 @@ Other workloads (`--workload`, one JSON line each; not the headline):
                  chunks so progress is printed;
   bake           light baking of the 512^3 cloud's single-scatter source on the
                  GPU (fld_light_bake), HIP-event timed, against the 24 bytes
-                 per voxel it must move.
+                 per voxel it must move;
+  render         primary ray-march of the 512^3 cloud's image (fld_render) from
+                 a fluence field, against its 32 bytes per voxel.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
        [--no-fp64] [--max-iters M] [--copy-bytes B] [--workload W]
@@ -135,7 +137,7 @@ def main():
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuner's cached launch shapes and schedule")
     ap.add_argument("--workload", default="cloud256",
-                    choices=["cloud256", "cloud128-fp64", "batch", "cloud512", "bake"])
+                    choices=["cloud256", "cloud128-fp64", "batch", "cloud512", "bake", "render"])
     ap.add_argument("--chunk", type=int, default=0,
                     help="outer iterations per call (0: one call); later calls resume")
     ap.add_argument("--sequential", action="store_true",
@@ -152,7 +154,7 @@ def main():
         args.max_iters = args.max_iters or 5000
         run_batch(args)
         return
-    if args.workload == "bake":
+    if args.workload in ("bake", "render"):
         run_bake(args)
         return
     if args.workload == "cloud128-fp64":
@@ -312,7 +314,7 @@ def main():
 
 
 def run_bake(args):
-    """GPU light baking of the 512^3 cloud (one JSON line)."""
+    """GPU light baking or ray-march render of the 512^3 cloud (one JSON line)."""
     import torch
     import paper_1403_8105_amd as F
     from synth import media
@@ -324,30 +326,47 @@ def run_bake(args):
     d_al = torch.from_numpy(al).to(dev)
     d_q = torch.empty_like(d_st)
     stream = torch.cuda.current_stream(dev)
-    for _ in range(max(args.warmup, 1)):
+    render = args.workload == "render"
+    if render:
+        # a smooth stand-in fluence; the cost does not depend on its values
+        d_phi = torch.from_numpy(media.value_noise(512, 2, 9)).to(dev)
+        d_img = torch.empty((512, 512), dtype=torch.float64, device=dev)
         F.fld_light_bake(d_st.data_ptr(), d_al.data_ptr(), 1.0, st.shape, h, d_q.data_ptr(),
                          stream.cuda_stream)
+
+    def once():
+        if render:
+            F.fld_render(d_st.data_ptr(), d_al.data_ptr(), d_q.data_ptr(), d_phi.data_ptr(), 1.0,
+                         st.shape, h, d_img.data_ptr(), stream.cuda_stream)
+        else:
+            F.fld_light_bake(d_st.data_ptr(), d_al.data_ptr(), 1.0, st.shape, h, d_q.data_ptr(),
+                             stream.cuda_stream)
+
+    for _ in range(max(args.warmup, 1)):
+        once()
     reps = max(args.steps, 1) * 10
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a.record(stream)
     for _ in range(reps):
-        F.fld_light_bake(d_st.data_ptr(), d_al.data_ptr(), 1.0, st.shape, h, d_q.data_ptr(),
-                         stream.cuda_stream)
+        once()
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
     n = st.size
-    alg = 24.0 * n
+    alg = (32.0 if render else 24.0) * n
     line = {
-        "metric": "voxels/s of GPU light baking (512^3 cloud)", "value": n / (ms * 1e-3),
+        "metric": ("voxels/s of the GPU primary ray-march (512^3 cloud, 512^2 image)" if render
+                   else "voxels/s of GPU light baking (512^3 cloud)"),
+        "value": n / (ms * 1e-3),
         "unit": "voxels/s", "n_gpus": 1, "steps": reps, "warmup": max(args.warmup, 1),
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "single-scatter source of a +z directional light over the "
-                               "512^3 cloud (7 octaves, sigma_t in [0,500], 60% near-vacuum, "
+        "config": {"workload": ("orthographic +z ray-march of " if render else
+                                "single-scatter source of a +z directional light over ") +
+                               "the 512^3 cloud (7 octaves, sigma_t in [0,500], 60% near-vacuum, "
                                "albedo 0.995)", "grid": list(st.shape)},
-        "roofline": {"bound": "hbm", "kernel": "k_light_bake", "achieved": alg / (ms * 1e-3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "k_render" if render else "k_light_bake", "achieved": alg / (ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg, "avg_launch_us": ms * 1e3},

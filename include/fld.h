@@ -224,6 +224,22 @@ fld_status fld_device_arch(int device, char *buf, int len);
 fld_status fld_light_bake(const double *d_sigma_t, const double *d_albedo, double light, int nx,
                           int ny, int nz, double h, double *d_q, void *hip_stream);
 
+/* Primary ray-march of the image from the fluence (Sec. 3): the radiance
+ * reaching the camera is the back-light attenuated by the whole ray plus,
+ * for every sample, Delta x T(sample -> camera) Q, with the source in terms
+ * of the diffusion solution 4 pi Q = q_ri + sigma_s phi + j.  Orthographic
+ * camera on the +z side: one ray per (i, j) column travelling +z; the
+ * sample of voxel k is attenuated by T = exp(-h (sigma_t(k)/2 +
+ * sum_{k' > k} sigma_t)); `background` enters at z = 0 and is attenuated by
+ * exp(-h sum_k sigma_t).  d_src holds q_ri + j (the emission given to the
+ * solver), d_phi the fluence, sigma_s = albedo * sigma_t; all nx*ny*nz
+ * float64, z fastest.  d_image: nx*ny float64, index i*ny + j.  Device
+ * pointers owned by the caller; enqueued on hip_stream, no wait.  Errors as
+ * for fld_light_bake (background must be finite and >= 0). */
+fld_status fld_render(const double *d_sigma_t, const double *d_albedo, const double *d_src,
+                      const double *d_phi, double background, int nx, int ny, int nz, double h,
+                      double *d_image, void *hip_stream);
+
 /* Batched solve: nvol volumes of sizes dims3[3v..3v+2] and edges h[v], each
  * with nchan colour channels that share the extinction field and have their
  * own albedo and emission (the per-channel albedo pattern of Sec. 6).  All

@@ -60,7 +60,7 @@ EXPORTS = ["fld_default_options", "fld_create", "fld_set_medium", "fld_set_mediu
            "fld_solve", "fld_solve_device", "fld_solve_resume", "fld_residual",
            "fld_residual_device", "fld_destroy", "fld_status_string", "fld_last_error",
            "fld_batch_create", "fld_batch_set_volume", "fld_batch_solve", "fld_batch_destroy",
-           "fld_batch_last_error", "fld_device_arch", "fld_light_bake"]
+           "fld_batch_last_error", "fld_device_arch", "fld_light_bake", "fld_render"]
 
 
 def lib():
@@ -75,6 +75,8 @@ def lib():
         L.fld_device_arch.argtypes = [C.c_int, C.c_char_p, C.c_int]
         L.fld_light_bake.argtypes = [vp, vp, C.c_double, C.c_int, C.c_int, C.c_int, C.c_double,
                                      vp, vp]
+        L.fld_render.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, C.c_int, C.c_int,
+                                 C.c_double, vp, vp]
         L.fld_create.argtypes = [C.POINTER(fld_options), C.c_int, C.c_int, C.c_int, C.c_double,
                                  C.POINTER(vp)]
         L.fld_set_medium.argtypes = [vp, vp, vp, vp]
@@ -245,6 +247,16 @@ def fld_light_bake(d_sigma_t: int, d_albedo: int, light: float, shape, h: float,
                              float(h), d_q or None, stream or None)
     if s != FLD_OK:
         raise FldError(s, "fld_light_bake")
+
+
+def fld_render(d_sigma_t: int, d_albedo: int, d_src: int, d_phi: int, background: float, shape,
+               h: float, d_image: int, stream: int = 0):
+    """Ray-march the (nx, ny) image of an orthographic camera along +z on the device."""
+    nx, ny, nz = shape
+    s = lib().fld_render(d_sigma_t or None, d_albedo or None, d_src or None, d_phi or None,
+                         float(background), nx, ny, nz, float(h), d_image or None, stream or None)
+    if s != FLD_OK:
+        raise FldError(s, "fld_render")
 
 
 def fld_status_string(s: int) -> str:

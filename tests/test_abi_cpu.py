@@ -79,3 +79,12 @@ def test_light_bake_rejects_invalid_arguments():
     assert L.fld_light_bake(1, 1, 1.0, 0, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
     assert L.fld_light_bake(1, 1, -1.0, 4, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
     assert L.fld_light_bake(1, 1, 1.0, 4, 4, 4, float("nan"), 1, None) == F.FLD_ERR_INVALID_ARGUMENT
+
+
+def test_render_rejects_invalid_arguments():
+    import paper_1403_8105_amd as F
+
+    L = F.lib()
+    assert L.fld_render(None, 1, 1, 1, 0.0, 4, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
+    assert L.fld_render(1, 1, 1, 1, -1.0, 4, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
+    assert L.fld_render(1, 1, 1, 1, 0.0, 4, 4, 0, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
