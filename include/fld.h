@@ -118,6 +118,10 @@ typedef struct fld_options {
                              factor; <= 0 never restarts (default 2)                       */
     double corr_scale;    /* multigrid: factor on the coarse-grid correction of the finest
                              level (piecewise-constant prolongation under-corrects; default 1) */
+    double anisotropy_g;  /* phase-function anisotropy g in [0,1): the diffusion coefficient
+                             and the Knudsen number use the reduced extinction
+                             sigma_t (1 - albedo g) (Sec. 7); absorption is unchanged.
+                             Batches need one channel per volume when g != 0 (default 0) */
 } fld_options;
 
 typedef struct fld_report {

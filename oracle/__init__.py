@@ -29,7 +29,8 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double),
                 ("limiter", C.c_int), ("larsen_n", C.c_double), ("eps", C.c_double),
                 ("sigma_eps", C.c_double), ("phi_b", C.c_double), ("mirror_d", C.c_int),
-                ("ghost_phi", _dp), ("jbar", C.c_double), ("jnorm", C.c_double)]
+                ("ghost_phi", _dp), ("jbar", C.c_double), ("jnorm", C.c_double),
+                ("aniso_g", C.c_double)]
 
 
 class SolveOpts(C.Structure):
@@ -147,12 +148,12 @@ class Problem:
 
 def setup(sigma_t, albedo, Q, h, limiter: str = "lp", larsen_n: float = 2.0, eps: float = 1e-20,
           sigma_eps: float = -1.0, phi_b: float = 0.0, mirror_d: bool = False,
-          ghost_phi=None) -> Problem:
+          ghost_phi=None, aniso_g: float = 0.0) -> Problem:
     sigma_t, albedo, Q = _f64(sigma_t), _f64(albedo), _f64(Q)
     nx, ny, nz = sigma_t.shape
     assert albedo.shape == sigma_t.shape == Q.shape
     p = Params(nx, ny, nz, float(h), LIMITERS[limiter], float(larsen_n), float(eps),
-               float(sigma_eps), float(phi_b), int(mirror_d), None, 0.0, 0.0)
+               float(sigma_eps), float(phi_b), int(mirror_d), None, 0.0, 0.0, float(aniso_g))
     if ghost_phi is not None:
         ghost_phi = _f64(ghost_phi)
         assert ghost_phi.shape == (nx + 2, ny + 2, nz + 2)

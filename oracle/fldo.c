@@ -143,9 +143,12 @@ int fldo_setup(fldo_params *p, const double *sigma_t, const double *albedo, cons
     double sum_j2 = 0.0;
     for (long c = 0; c < n; ++c) {
         /* Alg. 1 set-up: sigma <- max(sigma, sigma_eps); the clamped value is
-         * the sigma of the whole method, absorption term included. */
-        sig_hat[c] = fmax(sigma_t[c], p->sigma_eps);
-        sig_a[c] = (1.0 - albedo[c]) * sig_hat[c];
+         * the sigma of the whole method, absorption term included.  With a
+         * phase-function anisotropy g the diffusion coefficient and the
+         * Knudsen number use the reduced extinction sigma_t (1 - albedo g)
+         * (Sec. 7); the absorption (1 - albedo) sigma_t is not reduced. */
+        sig_hat[c] = fmax(sigma_t[c] * (1.0 - albedo[c] * p->aniso_g), p->sigma_eps);
+        sig_a[c] = (1.0 - albedo[c]) * fmax(sigma_t[c], p->sigma_eps);
         sum_j2 += Q[c] * Q[c];
     }
     p->jnorm = sqrt(sum_j2);

@@ -38,6 +38,7 @@ typedef struct fldo_params {
     const double *ghost_phi;  /* optional padded (nx+2)(ny+2)(nz+2) ghost fluence */
     double jbar;              /* RMS emission (set-up output) */
     double jnorm;             /* ||j||_2 (set-up output) */
+    double aniso_g;           /* phase-function anisotropy g: reduced extinction in D and R */
 } fldo_params;
 
 typedef struct fldo_solve_opts {

@@ -557,8 +557,8 @@ struct fld_engine_impl {
         // the fine list already holds exactly these tasks
         l.d = fine_tasks.d + fine_range[p];
         l.n = fine_range[p + 1] - fine_range[p];
-        launch_setup(stream, P.fine, l.d, l.n, d_st, d_al, d_q, V.sigma_eps, d_part[0] + fine_range[p],
-                     mixed);
+        launch_setup(stream, P.fine, l.d, l.n, d_st, d_al, d_q, V.sigma_eps, opt.anisotropy_g,
+                     d_part[0] + fine_range[p], mixed);
         launch_sum_partials(stream, 1, d_fine_range + p, d_part[0], d_scal + (size_t)p * S_COUNT,
                             S_JN2, nullptr);
         launch_after_setup(stream, 1, d_fines + p, d_scal + (size_t)p * S_COUNT);
@@ -1164,6 +1164,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->colour_split != 0 && o->colour_split != 1) { err = "colour_split must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!std::isfinite(o->restart_growth)) { err = "restart_growth must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->corr_scale > 0.0 && o->corr_scale <= 4.0)) { err = "corr_scale must lie in (0,4]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->anisotropy_g >= 0.0 && o->anisotropy_g < 1.0)) { err = "anisotropy_g must lie in [0,1)"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1271,6 +1272,7 @@ fld_status fld_default_options(fld_options *o)
     o->colour_split = 1;
     o->restart_growth = 2.0;
     o->corr_scale = 1.0;
+    o->anisotropy_g = 0.0;
     return FLD_OK;
 }
 
@@ -1554,6 +1556,12 @@ fld_status fld_batch_create(const fld_options *o, int nvol, const int *dims3, co
     fld_status s = validate_options(o, err);
     if (s == FLD_OK && o->method != FLD_METHOD_MG) {
         err = "batched solves use the multigrid method";
+        s = FLD_ERR_INVALID_ARGUMENT;
+    }
+    if (s == FLD_OK && o->anisotropy_g != 0.0 && nchan > 1) {
+        // the reduced extinction depends on each channel's albedo, while the
+        // channels of a volume share one extinction field
+        err = "batch: anisotropy_g != 0 needs one channel per volume";
         s = FLD_ERR_INVALID_ARGUMENT;
     }
     for (int v = 0; s == FLD_OK && v < nvol; ++v)

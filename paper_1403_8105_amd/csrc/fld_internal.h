@@ -94,7 +94,7 @@ enum Limiter { L_CDA = 0, L_LP = 1, L_SUM = 2, L_MAX = 3, L_KERSHAW = 4, L_LARSE
 // problem.
 void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
                   const double *sigma_t, const double *albedo, const double *Q,
-                  double sigma_eps, double *partials, int mixed);
+                  double sigma_eps, double aniso_g, double *partials, int mixed);
 void launch_sum_partials(hipStream_t s, int nprob, const int *range, const double *partials,
                          double *scal, int slot, const int *active);
 void launch_after_setup(hipStream_t s, int nprob, const Fine *fines, double *scal);

@@ -266,7 +266,7 @@ __device__ inline double limiter(int kind, double R, double n)
 
 __global__ void __launch_bounds__(kBlock)
 k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const double *albedo,
-        const double *Q, double sigma_eps, double *partials, float *sa32)
+        const double *Q, double sigma_eps, double aniso_g, double *partials, float *sa32)
 {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
@@ -274,10 +274,11 @@ k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const doub
         const Dec dec(f.ny, f.nz);
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
-            const double sh = fmax(sigma_t[c], sigma_eps);
+            // transport extinction (reduced by the anisotropy g, Sec. 7) for
+            // D and the Knudsen number; absorption from the clamped sigma_t
             if (f.write_sighat)
-                f.sig_hat[c] = sh;
-            const double sa = (1.0 - albedo[c]) * sh;
+                f.sig_hat[c] = fmax(sigma_t[c] * (1.0 - albedo[c] * aniso_g), sigma_eps);
+            const double sa = (1.0 - albedo[c]) * fmax(sigma_t[c], sigma_eps);
             f.sa64[c] = sa;
             if (sa32) {
                 long long o = c;
@@ -1824,10 +1825,10 @@ inline int grid_for(int ntasks)
 
 void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
                   const double *sigma_t, const double *albedo, const double *Q,
-                  double sigma_eps, double *partials, int mixed)
+                  double sigma_eps, double aniso_g, double *partials, int mixed)
 {
     hipLaunchKernelGGL(k_setup, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, f, tasks, ntasks,
-                       sigma_t, albedo, Q, sigma_eps, partials,
+                       sigma_t, albedo, Q, sigma_eps, aniso_g, partials,
                        mixed ? (float *)f.sa0 : (float *)nullptr);
 }
 

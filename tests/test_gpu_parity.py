@@ -347,3 +347,36 @@ def test_full_size_256_in_the_bench_configuration():
     assert rep["status"] == F.FLD_OK and rep["rel"] <= 1e-6
     _, rel_o, _ = oracle.nonlinear_residual(prob, phi)
     assert rel_o == pytest.approx(rep["rel"], rel=1e-9)
+
+
+@pytest.mark.parametrize("lim", ["sum", "max"])
+def test_residual_parity_remaining_limiters(lim):
+    shape = (21, 18, 13)
+    st, al, Q, h = ragged_cloud(shape)
+    rng = np.random.default_rng(2)
+    phi = rng.uniform(0.0, 1.0, shape) * (rng.random(shape) > 0.05)
+    prob = oracle.setup(st, al, Q, h, limiter=lim)
+    r_ref, rel_ref, _ = oracle.nonlinear_residual(prob, phi)
+    s = gpu_solver(shape, h, st, al, Q, limiter=lim, method="rbsor")
+    r, rel = s.residual(phi)
+    assert np.max(np.abs(r - r_ref)) <= 1e-12 * np.max(np.abs(r_ref))
+    assert rel == pytest.approx(rel_ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("g", [0.3, 0.8])
+def test_anisotropy_iterate_parity(g):
+    # reduced extinction in D and R: FP64 multigrid iterates follow the oracle
+    st, al, Q, h = ragged_cloud((32, 24, 32), seed=13)
+    prob = oracle.setup(st, al, Q, h, aniso_g=g)
+    for k in (1, 4, 12):
+        ref = oracle.solve(prob, method="mg", tol=0.0, max_iters=k)
+        s = gpu_solver(st.shape, h, st, al, Q, tol=0.0, max_iters=k, anisotropy_g=g)
+        phi, rep = s.solve()
+        np.testing.assert_allclose(rep["history"], ref.history, rtol=1e-9)
+        assert rel_l2(phi, ref.phi) <= 1e-10, k
+    # Algorithm 1 as well
+    ref = oracle.solve(prob, method="alg1", tol=0.0, max_iters=20, check_every=10 ** 6)
+    s = gpu_solver(st.shape, h, st, al, Q, method="rbsor", tol=0.0, max_iters=20,
+                   check_every=10 ** 6, anisotropy_g=g)
+    phi, _ = s.solve()
+    assert rel_l2(phi, ref.phi) <= 1e-12
