@@ -122,6 +122,11 @@ typedef struct fld_options {
                              and the Knudsen number use the reduced extinction
                              sigma_t (1 - albedo g) (Sec. 7); absorption is unchanged.
                              Batches need one channel per volume when g != 0 (default 0) */
+    int deep_cells;       /* multigrid launch shape: coarse levels from the first one with at
+                             most this many cells down to the coarsest run in one workgroup
+                             per problem (two launches instead of several per level); 0
+                             launches every level separately.  No result bit changes
+                             (default 4096)                                                */
 } fld_options;
 
 typedef struct fld_report {

@@ -37,7 +37,8 @@ class fld_options(C.Structure):
                 ("stream", C.c_void_p), ("timing", C.c_int), ("deflate_tau", C.c_double),
                 ("graph", C.c_int), ("task_cells0", C.c_int), ("coarse_blocks", C.c_int),
                 ("colour_split", C.c_int), ("restart_growth", C.c_double),
-                ("corr_scale", C.c_double), ("anisotropy_g", C.c_double)]
+                ("corr_scale", C.c_double), ("anisotropy_g", C.c_double),
+                ("deep_cells", C.c_int)]
 
 
 class fld_report(C.Structure):

@@ -45,6 +45,7 @@ struct Prob {
     int final_k = 0;     // iteration at which the problem stopped
     int status = FLD_OK;
     int gid0 = 0;        // index of its finest grid in the grid table
+    int deep = 0;        // first level of the deep part of the V-cycle (one workgroup)
 };
 
 struct Vol {
@@ -87,8 +88,9 @@ struct fld_engine_impl {
     std::vector<int> fine_range;   // host copy, nprob+1
     int *d_fine_range = nullptr;
     DevList mid[kMaxLevels], rest[kMaxLevels], gal[kMaxLevels];
-    int *d_chol_ids[kMaxLevels] = {};
-    int n_chol[kMaxLevels] = {};
+    DevList coarse_cells[kMaxLevels];   // every cell of level l+1 (deep levels included)
+    int *d_coarse_ids = nullptr, *d_deep_roots = nullptr;   // coarsest grids / deep roots
+    int n_coarse = 0, n_deep = 0;
     int max_coarse_n = 1, max_coarse_bw = 1;
     // kernel instance choice: kmode 0 FP64, 1 FP32 natural, 2 FP32 colour-split,
     // 3 FP32 per problem; lsp the same for the level kernels (0 / 1 / 2)
@@ -508,16 +510,42 @@ struct fld_engine_impl {
             HK(hipMemcpy(d_grids_defl, gd.data(), sizeof(Grid) * ngrids, hipMemcpyHostToDevice),
                "hipMemcpy grids");
         }
+        // deep part: from the first level (below the finest) with at most
+        // opt.deep_cells cells; levels above it use the work-list kernels
+        std::vector<int> roots, coarsest;
+        for (Prob &P : probs) {
+            P.deep = P.nlev - 1;
+            if (opt.deep_cells > 0)
+                for (int l = 1; l < P.nlev; ++l)
+                    if (P.lv[l].n <= opt.deep_cells) {
+                        P.deep = l;
+                        break;
+                    }
+            if (P.deep < P.nlev - 1)
+                roots.push_back(P.gid0 + P.deep);
+            coarsest.push_back(P.gid0 + P.nlev - 1);
+        }
+        n_deep = (int)roots.size();
+        if (n_deep) {
+            CK(dalloc(&d_deep_roots, sizeof(int) * n_deep));
+            HK(hipMemcpy(d_deep_roots, roots.data(), sizeof(int) * n_deep, hipMemcpyHostToDevice),
+               "hipMemcpy");
+        }
+        n_coarse = (int)coarsest.size();
+        CK(dalloc(&d_coarse_ids, sizeof(int) * n_coarse));
+        HK(hipMemcpy(d_coarse_ids, coarsest.data(), sizeof(int) * n_coarse, hipMemcpyHostToDevice),
+           "hipMemcpy");
         for (int l = 0; l < max_levels; ++l) {
-            std::vector<Task> m, r, g;
-            std::vector<int> ch;
+            std::vector<Task> m, r, g, cc;
             // launch shape: task sizes from the cells all problems hold at this level
             long long nm = 0, nr = 0, ng = 0;
             for (const Prob &P : probs)
                 if (l < P.nlev - 1) {
                     const Level &C = P.lv[l + 1];
-                    nm += P.lv[l].n;
-                    nr += C.n;
+                    if (l < P.deep) {
+                        nm += P.lv[l].n;
+                        nr += C.n;
+                    }
                     ng += (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
                 }
             const int tm = l == 0 ? opt.task_cells0 : coarse_task(nm, 512);
@@ -525,24 +553,20 @@ struct fld_engine_impl {
             for (int p = 0; p < nprob; ++p) {
                 const Prob &P = probs[p];
                 if (l < P.nlev - 1) {
-                    add_tasks(m, P.gid0 + l, P.lv[l].n, tm);
-                    add_tasks(r, P.gid0 + l + 1, P.lv[l + 1].n, tr);
+                    if (l < P.deep) {
+                        add_tasks(m, P.gid0 + l, P.lv[l].n, tm);
+                        add_tasks(r, P.gid0 + l + 1, P.lv[l + 1].n, tr);
+                    }
                     const Level &C = P.lv[l + 1];
                     add_tasks(g, P.gid0 + l + 1, (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1),
                               tg);
-                } else if (l == P.nlev - 1) {
-                    ch.push_back(P.gid0 + l);
+                    add_tasks(cc, P.gid0 + l + 1, C.n, 256);
                 }
             }
+            CK(upload_list(cc, coarse_cells[l]));
             CK(upload_list(m, mid[l]));
             CK(upload_list(r, rest[l]));
             CK(upload_list(g, gal[l]));
-            n_chol[l] = (int)ch.size();
-            if (!ch.empty()) {
-                CK(dalloc(&d_chol_ids[l], sizeof(int) * ch.size()));
-                HK(hipMemcpy(d_chol_ids[l], ch.data(), sizeof(int) * ch.size(),
-                             hipMemcpyHostToDevice), "hipMemcpy");
-            }
         }
         return FLD_OK;
     }
@@ -733,12 +757,13 @@ struct fld_engine_impl {
         CK(build_clusters());
         if (mg) {
             for (int l = 0; l + 1 < max_levels; ++l) {
-                if (!rest[l].n)
+                if (!coarse_cells[l].n)
                     continue;
                 if (mixed)
-                    launch_mean8_sa<float>(stream, d_grids[0], rest[l].d, rest[l].n);
+                    launch_mean8_sa<float>(stream, d_grids[0], coarse_cells[l].d, coarse_cells[l].n);
                 else
-                    launch_mean8_sa<double>(stream, d_grids[0], rest[l].d, rest[l].n);
+                    launch_mean8_sa<double>(stream, d_grids[0], coarse_cells[l].d,
+                                            coarse_cells[l].n);
             }
         }
         HK(hipGetLastError(), "medium launch");
@@ -820,9 +845,11 @@ struct fld_engine_impl {
                 }
                 launch_restrict<T>(stream, G, rest[l].d, rest[l].n, d_active, lsp);
             }
-            launch_coarse_solve<T>(stream, G, d_chol_ids[l], n_chol[l], d_active, d_fail,
-                                   max_coarse_n, max_coarse_bw);
         }
+        launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.nu1, opt.omega_s, true);
+        launch_coarse_solve<T>(stream, G, d_coarse_ids, n_coarse, d_active, d_fail, max_coarse_n,
+                               max_coarse_bw);
+        launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.nu2, opt.omega_s, false);
         for (int l = max_levels - 2; l >= 0; --l) {
             if (!mid[l].n)
                 continue;
@@ -1165,6 +1192,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (!std::isfinite(o->restart_growth)) { err = "restart_growth must be finite"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->corr_scale > 0.0 && o->corr_scale <= 4.0)) { err = "corr_scale must lie in (0,4]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->anisotropy_g >= 0.0 && o->anisotropy_g < 1.0)) { err = "anisotropy_g must lie in [0,1)"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->deep_cells < 0) { err = "deep_cells must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1273,6 +1301,7 @@ fld_status fld_default_options(fld_options *o)
     o->restart_growth = 2.0;
     o->corr_scale = 1.0;
     o->anisotropy_g = 0.0;
+    o->deep_cells = 4096;
     return FLD_OK;
 }
 

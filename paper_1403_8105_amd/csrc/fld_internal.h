@@ -151,6 +151,13 @@ template <typename T>
 void launch_mean8_sa(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks);
 // Coarsest level: one block per listed grid.  fail[prob] is set to 1 when a
 // pivot is not positive.
+// Deep part of the V-cycle, one workgroup per root (the first level of a
+// problem at or below the deep size limit): down (zero, nu pre-sweeps,
+// restrict) or up (prolong, nu post-sweeps) over the levels above the
+// coarsest.
+template <typename T>
+void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
+                 int nu, double omega, bool down);
 template <typename T>
 void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
                          const int *active, int *fail, int max_n, int max_bw);

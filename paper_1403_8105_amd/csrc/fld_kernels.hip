@@ -1664,6 +1664,133 @@ k_mean8_sa(const Grid *grids, const Task *tasks, int ntasks)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Deep part of the V-cycle.  Coarse levels of a few thousand cells are all
+// launch overhead, so one workgroup per problem runs every level from its
+// root (the first level at or below the size limit) down to the level above
+// the coarsest, and back up, with barriers between the phases.  The coarsest
+// solve between the two halves stays a kernel of its own.  Per cell the
+// arithmetic is exactly that of the level kernels (face coefficients, the
+// smoother's pair walk, the 8-child restriction, the parent prolongation).
+// ---------------------------------------------------------------------------
+constexpr int kDeepBlock = 1024;
+
+template <typename T>
+__device__ void deep_zero(const Grid &g)
+{
+    T *e = (T *)g.e;
+    for (long long c = threadIdx.x; c < g.n; c += blockDim.x)
+        e[c] = (T)0;
+}
+
+template <typename T>
+__device__ void deep_smooth(const Grid &g, int colour, T omega)
+{
+    T *e = (T *)g.e;
+    const Dec dec(g.ny, g.nz);
+    for (long long q = threadIdx.x; q < (g.n >> 1); q += blockDim.x) {
+        const long long c0 = 2 * q;
+        int i, j, k;
+        dec(c0, i, j, k);
+        const int odd = (i + j + colour) & 1;
+        const long long c = c0 + odd;
+        T num, den;
+        face_num_den<T>(g, e, c, i, j, k + odd, num, den);
+        e[c] = omega * (num / den) + ((T)1 - omega) * e[c];
+    }
+}
+
+// C.b = 8-child mean of the residual of F
+template <typename T>
+__device__ void deep_restrict(const Grid &F, const Grid &C)
+{
+    const T *e = (const T *)F.e;
+    T *bc = (T *)C.b;
+    const T h2 = (T)F.h2;
+    const Dec dec(C.ny, C.nz);
+    for (long long cc = threadIdx.x; cc < C.n; cc += blockDim.x) {
+        int I, J, K;
+        dec(cc, I, J, K);
+        T s = (T)0;
+        for (int di = 0; di < 2; ++di)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int dk = 0; dk < 2; ++dk) {
+                    const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+                    const long long c = ((long long)i * F.ny + j) * F.nz + k;
+                    T num, den;
+                    face_num_den<T>(F, e, c, i, j, k, num, den);
+                    s = s + (num - e[c] * den) / h2;
+                }
+        bc[cc] = (T)0.125 * s;
+    }
+}
+
+// F.e += C.e(parent)
+template <typename T>
+__device__ void deep_prolong(const Grid &F, const Grid &C)
+{
+    T *ef = (T *)F.e;
+    const T *ec = (const T *)C.e;
+    const T one = (T)1.0;
+    const Dec dec(F.ny, F.nz);
+    for (long long c = threadIdx.x; c < F.n; c += blockDim.x) {
+        int i, j, k;
+        dec(c, i, j, k);
+        ef[c] = ef[c] + one * ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
+    }
+}
+
+// Down: from the root, zero e, nu1 pre-sweeps (red then black), restrict,
+// to the level above the coarsest.
+template <typename T>
+__global__ void __launch_bounds__(kDeepBlock)
+k_deep_down(const Grid *grids, const int *roots, const int *active, int nu1, T omega)
+{
+    int gid = roots[blockIdx.x];
+    if (active && !active[grids[gid].prob])
+        return;
+    while (grids[gid].coarser >= 0) {
+        const Grid &g = grids[gid];
+        deep_zero<T>(g);
+        __syncthreads();
+        for (int s = 0; s < nu1; ++s) {
+            deep_smooth<T>(g, 0, omega);
+            __syncthreads();
+            deep_smooth<T>(g, 1, omega);
+            __syncthreads();
+        }
+        deep_restrict<T>(g, grids[g.coarser]);
+        __syncthreads();
+        gid = g.coarser;
+    }
+}
+
+// Up: from the level above the coarsest back to the root, prolongate and
+// nu2 post-sweeps (black then red).
+template <typename T>
+__global__ void __launch_bounds__(kDeepBlock)
+k_deep_up(const Grid *grids, const int *roots, const int *active, int nu2, T omega)
+{
+    const int root = roots[blockIdx.x];
+    if (active && !active[grids[root].prob])
+        return;
+    int gid = root;
+    while (grids[gid].coarser >= 0)
+        gid = grids[gid].coarser;          // the coarsest
+    while (gid != root) {
+        gid = grids[gid].finer;
+        const Grid &g = grids[gid];
+        deep_prolong<T>(g, grids[g.coarser]);
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s) {
+            deep_smooth<T>(g, 1, omega);
+            __syncthreads();
+            deep_smooth<T>(g, 0, omega);
+            __syncthreads();
+        }
+    }
+}
+
 // Coarsest level: e = M^{-1} (h^2 b) with M = h^2 A in natural order (half
 // bandwidth bw = ny*nz), factored by banded Cholesky in FP64 and solved in the
 // same launch.  Band entry (r, q), r - bw <= q <= r, sits at
@@ -1993,6 +2120,15 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
                            active, fail, max_n);
 }
 
+template <typename T>
+void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
+                 int nu, double omega, bool down)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(down ? k_deep_down<T> : k_deep_up<T>, dim3(count), dim3(kDeepBlock), 0, s,
+                           grids, roots, active, nu, (T)omega);
+}
+
 #define FLD_INSTANTIATE(T)                                                                       \
     template void launch_zero<T>(hipStream_t, const Grid *, const Task *, int, const int *);     \
     template void launch_smooth<T>(hipStream_t, const Grid *, const Task *, int, const int *,    \
@@ -2003,7 +2139,9 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
     template void launch_galerkin<T>(hipStream_t, const Grid *, const Task *, int, const int *, int); \
     template void launch_mean8_sa<T>(hipStream_t, const Grid *, const Task *, int);              \
     template void launch_coarse_solve<T>(hipStream_t, const Grid *, const int *, int,            \
-                                         const int *, int *, int, int);
+                                         const int *, int *, int, int);                          \
+    template void launch_deep<T>(hipStream_t, const Grid *, const int *, int, const int *, int,  \
+                                 double, bool);
 
 FLD_INSTANTIATE(float)
 FLD_INSTANTIATE(double)

@@ -269,16 +269,37 @@ def test_colour_split_is_bit_identical(shape, omega_s):
     np.testing.assert_array_equal(outs[1][1]["history"], outs[0][1]["history"])
 
 
-def test_launch_shapes_are_bit_identical():
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_launch_shapes_are_bit_identical(prec):
+    # task sizes and the one-workgroup deep part of the V-cycle change where
+    # and how work is launched, not what is computed
     st, al, Q, h = ragged_cloud((32, 32, 48), seed=9)
     outs = []
-    for tc0, cb in ((4096, 2048), (512, 64), (65536, 65536)):
-        s = gpu_solver(st.shape, h, st, al, Q, precision="mixed", tol=0.0, max_iters=6,
-                       task_cells0=tc0, coarse_blocks=cb)
+    for tc0, cb, deep in ((4096, 2048, 0), (512, 64, 4096), (65536, 65536, 100000),
+                          (4096, 2048, 1)):
+        s = gpu_solver(st.shape, h, st, al, Q, precision=prec, tol=0.0, max_iters=6,
+                       task_cells0=tc0, coarse_blocks=cb, deep_cells=deep)
         outs.append(s.solve())
     for phi, rep in outs[1:]:
         np.testing.assert_array_equal(phi, outs[0][0])
         np.testing.assert_array_equal(rep["history"], outs[0][1]["history"])
+
+
+def test_batch_deep_cycle_bit_identical():
+    vols = media.batch_config(nvol=3, size_scale=0.25, seed=5)
+    dims = [(v["n"],) * 3 for v in vols]
+    shapes = [d for d in dims for _ in range(3)]
+    res = []
+    for deep in (0, 4096):
+        o = F.fld_default_options(precision="mixed", tol=0.0, max_iters=5, deep_cells=deep)
+        b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
+        for i, v in enumerate(vols):
+            F.fld_batch_set_volume(b, i, v["sigma_t"], v["albedo"], v["Q"])
+        outs, _, _ = F.fld_batch_solve(b, shapes)
+        F.fld_batch_destroy(b)
+        res.append(outs)
+    for a, b_ in zip(*res):
+        np.testing.assert_array_equal(a, b_)
 
 
 def test_batch_mixing_split_and_natural_volumes():
