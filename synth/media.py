@@ -118,6 +118,26 @@ def point_source(n: int = 32, sigma_t: float = 10.0, albedo: float = 0.9, h: flo
     return st, al, Q, h
 
 
+def sphere_cloud(n, sigma_t: float = 10.0, albedo: float = 0.9, radius: float = 0.4,
+                 octaves: int = 3, seed: int = 7):
+    """The convergence test case of Sec. 5 (Fig. 3): a sphere of constant
+    extinction centred in the unit cube, vacuum (sigma_t = 0) outside, and an
+    emission field of fractal value noise inside the sphere only.  The paper
+    gives neither the extinction, the albedo nor the radius; these defaults
+    put about 8 optical depths across the sphere.  h = 1/n."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    h = 1.0 / max(nx, ny, nz)
+    x = (np.arange(nx) + 0.5) * h - 0.5 * nx * h
+    y = (np.arange(ny) + 0.5) * h - 0.5 * ny * h
+    z = (np.arange(nz) + 0.5) * h - 0.5 * nz * h
+    r2 = x[:, None, None] ** 2 + y[None, :, None] ** 2 + z[None, None, :] ** 2
+    inside = r2 <= radius * radius
+    st = np.where(inside, float(sigma_t), 0.0)
+    al = np.full_like(st, float(albedo))
+    Q = np.where(inside, value_noise((nx, ny, nz), octaves, seed), 0.0)
+    return st, al, Q, h
+
+
 def cloud_medium(n, octaves: int, sigma_max: float, p_vac: float, albedo: float, seed: int):
     """Heterogeneous cloud: (sigma_t, albedo, Q, h) with h = 1/n (unit cube)."""
     nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
