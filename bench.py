@@ -31,7 +31,12 @@ Other workloads (`--workload`, one JSON line each; not the headline):
                  GPU (fld_light_bake), HIP-event timed, against the 24 bytes
                  per voxel it must move;
   render         primary ray-march of the 512^3 cloud's image (fld_render) from
-                 a fluence field, against its 32 bytes per voxel.
+                 a fluence field, against its 32 bytes per voxel;
+  convergence    the convergence studies of Sec. 5 (Fig. 3) on the GPU:
+                 Algorithm 1 (FP64 red-black SOR) on the spherical cloud at 51^3
+                 for a range of SOR factors, iterations to 1e-6 against the grid
+                 size, and the effect of the extinction floor sigma_eps (sphere
+                 with Algorithm 1, 128^3 cloud with the mixed multigrid).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
        [--no-fp64] [--max-iters M] [--copy-bytes B] [--workload W]
@@ -112,10 +117,18 @@ def copy_calibration(nbytes, reps=5):
     n = nbytes // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
+    b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
     for _ in range(reps):
         b.copy_(a)
+    ev1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": reps}),
+    ms = ev0.elapsed_time(ev1) / reps
+    # the copy's own rate (read + write) is the practical ceiling beside the 8 TB/s peak
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": reps + 1,
+                      "ms_per_copy": ms, "copy_gb_per_s": 2.0 * n * 4 / (ms * 1e-3) / 1e9}),
           flush=True)
 
 
@@ -137,7 +150,8 @@ def main():
     ap.add_argument("--no-tuned", action="store_true",
                     help="ignore the autotuner's cached launch shapes and schedule")
     ap.add_argument("--workload", default="cloud256",
-                    choices=["cloud256", "cloud128-fp64", "batch", "cloud512", "bake", "render"])
+                    choices=["cloud256", "cloud128-fp64", "batch", "cloud512", "bake", "render",
+                             "convergence"])
     ap.add_argument("--chunk", type=int, default=0,
                     help="outer iterations per call (0: one call); later calls resume")
     ap.add_argument("--sequential", action="store_true",
@@ -156,6 +170,9 @@ def main():
         return
     if args.workload in ("bake", "render"):
         run_bake(args)
+        return
+    if args.workload == "convergence":
+        run_convergence(args)
         return
     if args.workload == "cloud128-fp64":
         args.n, args.precision, args.tol, cfg = 128, "fp64", 1e-8, "cloud128"
@@ -370,6 +387,75 @@ def run_bake(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": alg, "avg_launch_us": ms * 1e3},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_convergence(args):
+    """Sec. 5, Fig. 3 on the GPU: (a) Algorithm 1's residual against iterations
+    for several SOR factors omega at 51^3, (b) iterations to 1e-6 against the
+    grid size, (c) the effect of the extinction floor sigma_eps.  The medium of
+    (a) and (b) is the spherical cloud with a vacuum exterior and a noise
+    emission field; (c) runs it and the 128^3 cloud (mixed multigrid).  Every
+    solve starts from the paper's initial state; the residual is the true
+    nonlinear one, checked after every iteration."""
+    import paper_1403_8105_amd as F
+    from synth import media
+
+    allow = (F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED)
+    marks = (1e-2, 1e-4, 1e-6)
+
+    def alg1(n, limiter="lp", omega=1.0, sigma_eps_l=None, max_iters=50000):
+        st, al, Q, h = media.sphere_cloud(n)
+        kw = {} if sigma_eps_l is None else {"sigma_eps": sigma_eps_l / (h * n)}
+        s = F.Solver(st.shape, h, method="rbsor", limiter=limiter, omega=omega, tol=1e-6,
+                     max_iters=max_iters, check_every=1, **kw)
+        try:
+            s.set_medium(st, al, Q)
+            _, rep = s.solve(allow=allow)
+        finally:
+            s.close()
+        hist = rep["history"]
+        return {"n": n, "limiter": limiter, "omega": omega,
+                "status": F.fld_status_string(rep["status"]), "iterations": rep["iterations"],
+                "rel": rep["rel"], "time_ms": rep["time_ms"],
+                "voxel_updates_per_s": rep["voxel_updates"] / max(rep["time_ms"], 1e-9) * 1e3,
+                "iterations_to": {f"{m:g}": (int(np.argmax(hist <= m)) if (hist <= m).any()
+                                             else None) for m in marks}}
+
+    log("bench: Fig. 3a, SOR factors at 51^3")
+    e1 = [alg1(51, lim, om) for lim in ("lp", "cda")
+          for om in (1.0, 1.2, 1.4, 1.5, 1.6, 1.7, 1.8, 1.9)]
+    log("bench: Fig. 3b, grid sizes")
+    e2 = [alg1(n, "lp", om) for om in (1.0, 1.5) for n in (17, 25, 33, 41, 51, 65, 81)]
+    log("bench: Fig. 3c, extinction floor")
+    floors = (1e-1, 1e-2, 1e-3, 1e-4, 1e-5)
+    e3_sphere = [dict(alg1(51, "lp", 1.0, se), sigma_eps_times_L=se) for se in floors]
+    st, al, Q, h = media.config("cloud128")
+    e3_cloud = []
+    for se in floors:
+        s = F.Solver(st.shape, h, precision="mixed", tol=1e-6, max_iters=5000,
+                     sigma_eps=se / (h * st.shape[0]))
+        try:
+            s.set_medium(st, al, Q)
+            _, rep = s.solve(allow=allow)
+        finally:
+            s.close()
+        e3_cloud.append({"sigma_eps_times_L": se, "status": F.fld_status_string(rep["status"]),
+                         "iterations": rep["iterations"], "rel": rep["rel"],
+                         "time_ms": rep["time_ms"]})
+    ref = e1[0]
+    line = {
+        "metric": "voxel-updates/s of Algorithm 1 (FP64 red-black SOR, omega 1) on the 51^3 "
+                  "spherical cloud to 1e-6",
+        "value": ref["voxel_updates_per_s"], "unit": "voxel-updates/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": ref["time_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "sphere of radius 0.4 (sigma_t 10, albedo 0.9) in vacuum with a "
+                               "3-octave noise emission, unit cube, LP and CDA limiters; "
+                               "128^3 cloud (5 octaves, sigma_t in [0,200]) for sigma_eps"},
+        "fig3a_omega": e1, "fig3b_grid": e2, "fig3c_sigma_eps_sphere": e3_sphere,
+        "fig3c_sigma_eps_cloud128_mixed_mg": e3_cloud,
     }
     print(json.dumps(line), flush=True)
 
