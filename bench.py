@@ -292,6 +292,7 @@ def main():
         "time_to_tol_ms": ms_step,
         "converged": ok,
         "outer_iterations": reps[-1]["iterations"],
+        "nested_iterations": reps[-1].get("nested_iterations", 0),
         "final_rel": reps[-1]["rel"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -301,7 +302,10 @@ def main():
         "config": {"workload": f"cloud {n}^3 FLD (Levermore-Pomraning), {desc}, "
                                f"Beer-Lambert source; {args.precision} Picard multigrid "
                                f"V({tuned[args.precision].get('nu1', 2)},"
-                               f"{tuned[args.precision].get('nu2', 2)}) to rel {args.tol:g}",
+                               f"{tuned[args.precision].get('nu2', 2)}) to rel {args.tol:g}"
+                               + (f", started from the 2:1 coarser solve to "
+                                  f"{tuned[args.precision]['nested_tol']:g}"
+                                  if tuned[args.precision].get("nested_tol") else ""),
                    "grid": [n, n, n], "tol": args.tol, "precision": args.precision,
                    "tuned_options": tuned[args.precision],
                    "tuned_on_grid": tuned_from[args.precision]},

@@ -127,6 +127,15 @@ typedef struct fld_options {
                              per problem (two launches instead of several per level); 0
                              launches every level separately.  No result bit changes
                              (default 4096)                                                */
+    double nested_tol;    /* multigrid grid sequencing: > 0 makes a solve from the paper's
+                             initial state first solve the medium coarsened 2:1 (sigma_t and
+                             Q averaged over the 8 children, albedo so that absorption is
+                             averaged too; default schedule, at most 10000 iterations) to
+                             this relative residual, and start from its fluence, constant
+                             over each 2x2x2 block.  Needs
+                             every axis even and anisotropy_g = 0; set up by fld_set_medium
+                             in a second, coarse context (1/8 of the memory); single-volume
+                             contexts only.  0 disables (default)                           */
 } fld_options;
 
 typedef struct fld_report {
@@ -147,6 +156,8 @@ typedef struct fld_report {
     double kernel_ms[4];
     double kernel_launches[4];
     double kernel_bytes[4];
+    int nested_iterations;/* outer iterations of the coarse solve of grid sequencing (0 when
+                             it did not run); included in time_ms and voxel_updates      */
 } fld_report;
 
 typedef struct fld_context fld_context;

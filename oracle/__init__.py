@@ -332,14 +332,56 @@ class SolveResult:
     rel: float
     rel_sweep: float
     history: np.ndarray
+    nested_iterations: int = 0
 
 
-def solve(prob: Problem, method: str = "mg", phi=None, D=None, hist_cap: int = 100000, **kw):
+def nested_problem(prob: Problem) -> Problem:
+    """The 2:1 coarser problem of grid sequencing (our design; the paper has no
+    multigrid): coarse cell C averages its 8 children, sigma_t = mean(sig_hat),
+    Q = mean(j), albedo = 1 - mean(sig_a)/mean(sig_hat) (so the absorption is
+    the mean of the fine one), voxel size 2h; the other parameters as given."""
+    nx, ny, nz = prob.shape
+    assert nx % 2 == 0 and ny % 2 == 0 and nz % 2 == 0, "grid sequencing needs even axes"
+
+    def mean8(a):
+        b = a.reshape(nx // 2, 2, ny // 2, 2, nz // 2, 2)
+        acc = np.zeros((nx // 2, ny // 2, nz // 2))
+        for di in range(2):
+            for dj in range(2):
+                for dk in range(2):
+                    acc = acc + b[:, di, :, dj, :, dk]
+        return acc / 8.0
+
+    s, a, q = mean8(prob.sig_hat), mean8(prob.sig_a), mean8(prob.j)
+    albedo = np.clip(1.0 - a / s, 0.0, 1.0)
+    pr = prob.params
+    inv = {v: k for k, v in LIMITERS.items()}
+    return setup(s, albedo, q, 2.0 * pr.h, limiter=inv[pr.limiter], larsen_n=pr.larsen_n,
+                 eps=pr.eps, sigma_eps=pr.sigma_eps, phi_b=pr.phi_b, mirror_d=bool(pr.mirror_d))
+
+
+def solve(prob: Problem, method: str = "mg", phi=None, D=None, hist_cap: int = 100000,
+          nested_tol: float = 0.0, **kw):
     """Run Algorithm 1 (method='alg1') or Picard-multigrid (method='mg').
 
     phi/D: start state (default: the paper's initialisation).  Returns the
     final state and the relative-residual history (one entry per check).
+    nested_tol > 0 (multigrid from the paper's initialisation): grid
+    sequencing -- first solve nested_problem(prob) with the default schedule
+    to nested_tol (at most 10000 iterations) and start from its fluence,
+    constant over each 2x2x2 block;
+    the result's ``nested_iterations`` counts the coarse iterations.
     """
+    if nested_tol > 0.0 and phi is None and method == "mg":
+        coarse = nested_problem(prob)
+        ck = {k: kw[k] for k in ("deflate_tau", "max_coarsest") if k in kw}
+        rc = solve(coarse, method="mg", tol=nested_tol, max_iters=10000, **ck)
+        start = rc.phi.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2)
+        if rc.status == "diverged":
+            start = None
+        res = solve(prob, method=method, phi=start, D=D, hist_cap=hist_cap, **kw)
+        res.nested_iterations = rc.iterations
+        return res
     phi0, D0 = prob.init_state()
     phi = phi0 if phi is None else _f64(phi).copy()
     D = D0 if D is None else _f64(D).copy()

@@ -38,7 +38,7 @@ class fld_options(C.Structure):
                 ("graph", C.c_int), ("task_cells0", C.c_int), ("coarse_blocks", C.c_int),
                 ("colour_split", C.c_int), ("restart_growth", C.c_double),
                 ("corr_scale", C.c_double), ("anisotropy_g", C.c_double),
-                ("deep_cells", C.c_int)]
+                ("deep_cells", C.c_int), ("nested_tol", C.c_double)]
 
 
 class fld_report(C.Structure):
@@ -47,7 +47,7 @@ class fld_report(C.Structure):
                 ("history_cap", C.c_int), ("history_len", C.c_int), ("time_ms", C.c_double),
                 ("voxel_updates", C.c_double), ("bytes", C.c_double),
                 ("kernel_ms", C.c_double * 4), ("kernel_launches", C.c_double * 4),
-                ("kernel_bytes", C.c_double * 4)]
+                ("kernel_bytes", C.c_double * 4), ("nested_iterations", C.c_int)]
 
 
 class FldError(RuntimeError):
@@ -178,7 +178,7 @@ def _report_dict(rep, hist):
             "rel_sweep": rep.rel_sweep, "history": hist[:min(rep.history_len, len(hist))].copy(),
             "time_ms": rep.time_ms, "voxel_updates": rep.voxel_updates,
             "kernel_ms": list(rep.kernel_ms), "kernel_launches": list(rep.kernel_launches),
-            "kernel_bytes": list(rep.kernel_bytes)}
+            "kernel_bytes": list(rep.kernel_bytes), "nested_iterations": rep.nested_iterations}
 
 
 def fld_solve(ctx, shape, phi_init=None, allow=(FLD_OK, FLD_ERR_NOT_CONVERGED)):

@@ -9,10 +9,13 @@ in device memory:
 2. Smoothing schedule (``nu1``, ``nu2``, ``omega_s``) and the growth
    factor that restarts the conjugate-gradient direction
    (``restart_growth``; restarts are never switched off), then the factor on
-   the finest coarse-grid correction (``corr_scale``) for the winner.  These
-   change the iteration, so every candidate runs a full solve to the
-   tolerance with the phase-1 shape; the shortest time to tolerance wins.
-   ``quick`` keeps the default schedule and tunes only ``corr_scale``.
+   the finest coarse-grid correction (``corr_scale``) for the winner, then
+   grid sequencing (``nested_tol``: first solve the 2:1 coarser medium to
+   this tolerance).  These change the iteration, so every candidate runs a
+   full solve to the tolerance with the phase-1 shape; the shortest time to
+   tolerance wins.  ``quick`` keeps the default schedule and tunes only
+   ``corr_scale`` and ``nested_tol``; ``refine`` starts from the cached
+   entry and tries only ``nested_tol``.
 
 The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
 limiter), in ``tuned.json`` beside this file unless another path is given.
@@ -38,6 +41,7 @@ SCHEDULES = [(2, 2, 1.0), (1, 1, 1.0), (2, 1, 1.0), (1, 2, 1.0), (3, 3, 1.0), (2
              (3, 3, 1.15), (4, 4, 1.0)]
 GROWTHS = [2.0, 10.0]
 SCALES = [1.0, 1.2, 1.4, 1.6, 1.8]
+NESTED = [1e-3, 1e-2]
 DEFAULT_SCHEDULE = (2, 2, 1.0, 2.0)
 
 
@@ -85,7 +89,7 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
          probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
-         quick: bool = False) -> dict:
+         quick: bool = False, refine: bool = False) -> dict:
     """Tune one grid/medium; stores and returns the cache entry."""
     import torch
 
@@ -97,31 +101,45 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     stream = torch.cuda.current_stream(dev).cuda_stream
     ptrs = [t.data_ptr() for t in d]
     base = dict(precision=precision, limiter=limiter)
+    even = all(x % 2 == 0 for x in sigma_t.shape)
+    key = cache_key(device_arch(), sigma_t.shape, precision, limiter)
+    old = load_cache(path or CACHE).get(key) if refine else None
+    if refine and not old:
+        raise RuntimeError(f"autotune: --refine needs a cached entry for {key}")
 
     # phase 1: launch shapes, time per outer iteration of a capped solve
     shape_ms = {}
-    for tc0, cb in SHAPES:
-        o = dict(base, tol=0.0, max_iters=probe_iters, task_cells0=tc0, coarse_blocks=cb)
-        _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)      # warm
-        ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
-        shape_ms[(tc0, cb)] = ms / max(rep["iterations"], 1)
-        log(f"autotune: task_cells0={tc0} coarse_blocks={cb}: {shape_ms[(tc0, cb)]:.4f} ms/it")
-    tc0, cb = min(shape_ms, key=shape_ms.get)
+    if old:
+        tc0, cb = old["options"]["task_cells0"], old["options"]["coarse_blocks"]
+        shape_ms = {tuple(int(v) for v in k.split(",")): ms
+                    for k, ms in old.get("shape_ms_per_iteration", {}).items()}
+    else:
+        for tc0, cb in SHAPES:
+            o = dict(base, tol=0.0, max_iters=probe_iters, task_cells0=tc0, coarse_blocks=cb)
+            _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)      # warm
+            ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
+            shape_ms[(tc0, cb)] = ms / max(rep["iterations"], 1)
+            log(f"autotune: task_cells0={tc0} coarse_blocks={cb}: "
+                f"{shape_ms[(tc0, cb)]:.4f} ms/it")
+        tc0, cb = min(shape_ms, key=shape_ms.get)
 
     # phase 2: schedules and restart factors, then the correction factor;
     # full solves to tol
     results = []
 
-    def run(nu1, nu2, ws, gr, sc):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0):
         o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
-                 nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc)
+                 nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc, nested_tol=nt)
         ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "ms": ms, "iterations": rep["iterations"],
+                        "corr_scale": sc, "nested_tol": nt, "ms": ms,
+                        "iterations": rep["iterations"],
+                        "nested_iterations": rep.get("nested_iterations", 0),
                         "rel": rep["rel"], "converged": ok})
-        log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} corr_scale={sc}: "
-            f"{rep['iterations']} its, rel {rep['rel']:.2e}, {ms:.0f} ms"
+        log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} corr_scale={sc} "
+            f"nested_tol={nt}: {rep['iterations']} its "
+            f"(+{rep.get('nested_iterations', 0)} coarse), rel {rep['rel']:.2e}, {ms:.0f} ms"
             f"{'' if ok else ' (not converged)'}")
         return results[-1] if ok else None
 
@@ -129,7 +147,10 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         return a if b is None or (a is not None and a["ms"] < b["ms"]) else b
 
     best = None
-    if quick:
+    if old:
+        oo = old["options"]
+        best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"])
+    elif quick:
         best = run(*DEFAULT_SCHEDULE, 1.0)
     else:
         for nu1, nu2, ws in SCHEDULES:
@@ -137,23 +158,30 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                 best = better(run(nu1, nu2, ws, gr, 1.0), best)
     if best is None:
         raise RuntimeError("autotune: no schedule reached the tolerance")
-    for sc in SCALES[1:]:
-        best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"], sc),
-                      best)
+    if not old:
+        for sc in SCALES[1:]:
+            best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
+                              sc), best)
+    if even:
+        for nt in NESTED:
+            best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
+                              best["corr_scale"], nt), best)
+    opts = {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"], "nu2": best["nu2"],
+            "omega_s": best["omega_s"], "restart_growth": best["restart_growth"],
+            "corr_scale": best["corr_scale"]}
+    if best.get("nested_tol"):
+        opts["nested_tol"] = best["nested_tol"]
     entry = {
-        "options": {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"],
-                    "nu2": best["nu2"], "omega_s": best["omega_s"],
-                    "restart_growth": best["restart_growth"], "corr_scale": best["corr_scale"]},
+        "options": opts,
         "tol": tol,
         "ms_to_tol": best["ms"],
         "iterations": best["iterations"],
         "shape_ms_per_iteration": {f"{a},{b}": v for (a, b), v in shape_ms.items()},
-        "schedules": results,
+        "schedules": (old.get("schedules", []) if old else []) + results,
     }
     if path:
-        arch = device_arch()
         cache = load_cache(path)
-        cache[cache_key(arch, sigma_t.shape, precision, limiter)] = entry
+        cache[key] = entry
         with open(path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return entry
@@ -170,6 +198,8 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true",
                     help="default schedule; tune launch shapes and corr_scale only")
     ap.add_argument("--max-iters", type=int, default=5000)
+    ap.add_argument("--refine", action="store_true",
+                    help="start from the cached entry; try only grid sequencing")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from synth import media
@@ -177,7 +207,7 @@ def main(argv=None):
     st, al, Q, h = media.config(args.workload, n=args.n)
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
-                 max_iters=args.max_iters)
+                 max_iters=args.max_iters, refine=args.refine)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"]}), flush=True)
 

@@ -1154,6 +1154,10 @@ struct fld_engine_impl {
 struct fld_context {
     fld_engine_impl eng;
     bool has_medium = false;
+    // grid sequencing: the 2:1 coarser problem and its medium arrays
+    fld_context *nested = nullptr;
+    double *d_nested_medium = nullptr;   // sigma_t, albedo, Q of the coarse grid
+    ~fld_context();
 };
 
 struct fld_batch {
@@ -1193,6 +1197,9 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (!(o->corr_scale > 0.0 && o->corr_scale <= 4.0)) { err = "corr_scale must lie in (0,4]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->anisotropy_g >= 0.0 && o->anisotropy_g < 1.0)) { err = "anisotropy_g must lie in [0,1)"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->deep_cells < 0) { err = "deep_cells must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->nested_tol >= 0.0 && std::isfinite(o->nested_tol))) { err = "nested_tol must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->nested_tol > 0.0 && o->method != FLD_METHOD_MG) { err = "nested_tol needs the multigrid method"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->nested_tol > 0.0 && o->anisotropy_g != 0.0) { err = "nested_tol needs anisotropy_g = 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1302,10 +1309,19 @@ fld_status fld_default_options(fld_options *o)
     o->corr_scale = 1.0;
     o->anisotropy_g = 0.0;
     o->deep_cells = 4096;
+    o->nested_tol = 0.0;
     return FLD_OK;
 }
 
 static thread_local std::string g_create_err;
+
+fld_context::~fld_context()
+{
+    if (nested)
+        delete nested;
+    if (d_nested_medium)
+        hipFree(d_nested_medium);
+}
 
 fld_status fld_create(const fld_options *o, int nx, int ny, int nz, double h, fld_context **out)
 {
@@ -1316,6 +1332,10 @@ fld_status fld_create(const fld_options *o, int nx, int ny, int nz, double h, fl
     fld_status s = validate_options(o, err);
     if (s == FLD_OK)
         s = validate_grid(o, nx, ny, nz, h, err);
+    if (s == FLD_OK && o->nested_tol > 0.0 && ((nx | ny | nz) & 1)) {
+        err = "nested_tol needs every axis even";
+        s = FLD_ERR_INVALID_ARGUMENT;
+    }
     if (s != FLD_OK) {
         g_create_err = err;
         return s;
@@ -1329,6 +1349,41 @@ fld_status fld_create(const fld_options *o, int nx, int ny, int nz, double h, fl
         g_create_err = c->eng.err;
         delete c;
         return s;
+    }
+    if (o->nested_tol > 0.0) {
+        // the coarse problem: same physics and precision, default launch
+        // shapes and schedule, solved to nested_tol without timing
+        fld_options co;
+        fld_default_options(&co);
+        co.limiter = o->limiter;
+        co.larsen_n = o->larsen_n;
+        co.eps = o->eps;
+        co.sigma_eps = o->sigma_eps;
+        co.phi_b = o->phi_b;
+        co.boundary_d = o->boundary_d;
+        co.precision = o->precision;
+        co.max_coarsest = o->max_coarsest;
+        co.max_iters = 10000;              // not the fine cap: chunked solves stay nested
+        co.tol = o->nested_tol;
+        co.device = o->device;
+        co.stream = o->stream;
+        co.deflate_tau = o->deflate_tau;
+        co.graph = o->graph;
+        co.colour_split = o->colour_split;
+        s = fld_create(&co, nx / 2, ny / 2, nz / 2, 2.0 * h, &c->nested);
+        if (s == FLD_OK) {
+            const size_t nc = (size_t)(nx / 2) * (ny / 2) * (nz / 2);
+            if (hipMalloc((void **)&c->d_nested_medium, 3 * 8 * nc) != hipSuccess) {
+                g_create_err = "grid sequencing: coarse medium allocation failed";
+                s = FLD_ERR_OUT_OF_MEMORY;
+            }
+        } else {
+            g_create_err = "grid sequencing: " + g_create_err;
+        }
+        if (s != FLD_OK) {
+            delete c;
+            return s;
+        }
     }
     *out = c;
     return FLD_OK;
@@ -1385,6 +1440,20 @@ static fld_status set_medium_impl(fld_context *c, const double *st, const double
     if (!device) {
         hipFree(dst); hipFree(dal); hipFree(dq);
     }
+    if (s == FLD_OK && c->nested) {
+        // the coarse problem's medium, averaged from the finest set-up fields
+        const Vol &V = E.vols[0];
+        const Fine &f = E.probs[0].fine;
+        const size_t nc = (size_t)(V.nx / 2) * (V.ny / 2) * (V.nz / 2);
+        double *cst = c->d_nested_medium, *cal = cst + nc, *cq = cal + nc;
+        launch_nested_coarsen(E.stream, f.sig_hat, f.sa64, f.j, V.nx, V.ny, V.nz, cst, cal, cq);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return E.hip_fail(e, "grid sequencing: coarsen launch");
+        s = set_medium_impl(c->nested, cst, cal, cq, true, E.stream);
+        if (s != FLD_OK)
+            return E.fail(s, "grid sequencing: coarse medium: %s", c->nested->eng.err.c_str());
+    }
     if (s == FLD_OK)
         c->has_medium = true;
     return s;
@@ -1432,10 +1501,34 @@ static fld_status solve_impl(fld_context *c, const double *phi_init, bool init_d
         E.probs[0].hist.assign(1, 0.0);
         E.solved_once = true;
         fill_report(rep, E, 0, FLD_OK, 0.0, 0.0, NAN);
+        if (rep && rep->struct_size == sizeof(fld_report))
+            rep->nested_iterations = 0;
         return FLD_OK;
     }
     int start = resume ? 2 : (phi_init ? 1 : 0);
-    if (start == 1) {
+    int nested_its = 0;
+    double nested_updates = 0.0;
+    if (start == 0 && c->nested) {
+        // grid sequencing: solve the coarse problem, start from its fluence
+        fld_report cr;
+        std::memset(&cr, 0, sizeof cr);
+        cr.struct_size = sizeof cr;
+        s = solve_impl(c->nested, nullptr, false, nullptr, false, 0, &cr);
+        if (s != FLD_OK && s != FLD_ERR_NOT_CONVERGED && s != FLD_ERR_DIVERGED)
+            return E.fail(s, "grid sequencing: coarse solve: %s", c->nested->eng.err.c_str());
+        nested_its = cr.iterations;
+        nested_updates = cr.voxel_updates;
+        if (s != FLD_ERR_DIVERGED) {
+            const Vol &V = E.vols[0];
+            launch_nested_prolong(E.stream, c->nested->eng.current_phi(0), V.nx, V.ny, V.nz,
+                                  E.probs[0].fine.phi[0]);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return E.hip_fail(e, "grid sequencing: prolong launch");
+            start = 1;
+        }
+    }
+    if (start == 1 && phi_init) {
         hipError_t e = hipMemcpyAsync(E.probs[0].fine.phi[0], phi_init, 8 * n,
                                       init_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                       E.stream);
@@ -1460,7 +1553,9 @@ static fld_status solve_impl(fld_context *c, const double *phi_init, bool init_d
     const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     const int st = E.probs[0].status;
-    fill_report(rep, E, 0, st, ms, updates, rel_sweep);
+    fill_report(rep, E, 0, st, ms, updates + nested_updates, rel_sweep);
+    if (rep && rep->struct_size == sizeof(fld_report))
+        rep->nested_iterations = nested_its;
     if (st == FLD_ERR_NOT_CONVERGED)
         E.fail(FLD_ERR_NOT_CONVERGED, "not converged after %d iterations (rel %g)",
                E.probs[0].final_k, E.probs[0].hist.empty() ? NAN : E.probs[0].hist.back());
@@ -1585,6 +1680,10 @@ fld_status fld_batch_create(const fld_options *o, int nvol, const int *dims3, co
     fld_status s = validate_options(o, err);
     if (s == FLD_OK && o->method != FLD_METHOD_MG) {
         err = "batched solves use the multigrid method";
+        s = FLD_ERR_INVALID_ARGUMENT;
+    }
+    if (s == FLD_OK && o->nested_tol > 0.0) {
+        err = "batch: grid sequencing (nested_tol) is for single-volume contexts";
         s = FLD_ERR_INVALID_ARGUMENT;
     }
     if (s == FLD_OK && o->anisotropy_g != 0.0 && nchan > 1) {

@@ -125,6 +125,13 @@ void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const i
                         const double *pd, const double *ps, double *alpha, const int *active);
 void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                        const int *active, int b0_idx, const double *alpha, int mixed);
+// Grid sequencing: the 2:1 coarsened medium (sigma_t, albedo, Q) from the
+// finest set-up fields, and the coarse fluence copied onto its 2x2x2 blocks.
+void launch_nested_coarsen(hipStream_t s, const double *sig_hat, const double *sa,
+                           const double *j, int nx, int ny, int nz, double *st_c, double *al_c,
+                           double *q_c);
+void launch_nested_prolong(hipStream_t s, const double *phi_c, int nx, int ny, int nz,
+                           double *phi);
 void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const double *scal, int colour, double omega, double *partials);
 

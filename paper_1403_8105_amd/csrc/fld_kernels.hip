@@ -980,6 +980,51 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
     }
 }
 
+// Grid sequencing: the medium of a 2:1 coarser grid from the finest
+// level's set-up fields, and the coarse fluence back on the fine grid.
+// Coarse cell C averages its 8 children: sigma_t = mean(sig_hat) (already at
+// or above the floor, so the coarse set-up keeps it), Q = mean(j), and the
+// albedo 1 - mean(sa)/mean(sig_hat) makes the coarse absorption the mean of
+// the fine one.
+__global__ void __launch_bounds__(kBlock)
+k_nested_coarsen(const double *__restrict__ sig_hat, const double *__restrict__ sa,
+                 const double *__restrict__ j, int nx, int ny, int nz, double *__restrict__ st_c,
+                 double *__restrict__ al_c, double *__restrict__ q_c)
+{
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    const long long nc = (long long)cx * cy * cz;
+    for (long long C = blockIdx.x * (long long)blockDim.x + threadIdx.x; C < nc;
+         C += (long long)gridDim.x * blockDim.x) {
+        const int K = (int)(C % cz), J = (int)((C / cz) % cy), I = (int)(C / ((long long)cy * cz));
+        double s = 0.0, a = 0.0, q = 0.0;
+        for (int di = 0; di < 2; ++di)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int dk = 0; dk < 2; ++dk) {
+                    const long long c =
+                        ((long long)(2 * I + di) * ny + (2 * J + dj)) * nz + (2 * K + dk);
+                    s = s + sig_hat[c];
+                    a = a + sa[c];
+                    q = q + j[c];
+                }
+        st_c[C] = s / 8.0;
+        al_c[C] = s > 0.0 ? fmin(fmax(1.0 - a / s, 0.0), 1.0) : 0.0;
+        q_c[C] = q / 8.0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_nested_prolong(const double *__restrict__ phi_c, int nx, int ny, int nz,
+                 double *__restrict__ phi)
+{
+    const long long n = (long long)nx * ny * nz;
+    const int cy = ny / 2, cz = nz / 2;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
+         c += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(c % nz), jj = (int)((c / nz) % ny), i = (int)(c / ((long long)ny * nz));
+        phi[c] = phi_c[((long long)(i / 2) * cy + jj / 2) * cz + k / 2];
+    }
+}
+
 // Algorithm 1, one colour: per voxel Knudsen number from the current
 // fluence, D_p update, face coefficients with the neighbours' stored D,
 // residual with the pre-update phi_p, SOR blend of numerator/denominator.
@@ -2033,6 +2078,25 @@ void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int 
 {
     hipLaunchKernelGGL(FLD_PICK(k_defl_apply, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, b0_idx, alpha);
+}
+
+void launch_nested_coarsen(hipStream_t s, const double *sig_hat, const double *sa,
+                           const double *j, int nx, int ny, int nz, double *st_c, double *al_c,
+                           double *q_c)
+{
+    const long long nc = (long long)(nx / 2) * (ny / 2) * (nz / 2);
+    const long long blocks = (nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_nested_coarsen, dim3((int)std::min<long long>(blocks, 65536)),
+                       dim3(kBlock), 0, s, sig_hat, sa, j, nx, ny, nz, st_c, al_c, q_c);
+}
+
+void launch_nested_prolong(hipStream_t s, const double *phi_c, int nx, int ny, int nz,
+                           double *phi)
+{
+    const long long n = (long long)nx * ny * nz;
+    const long long blocks = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_nested_prolong, dim3((int)std::min<long long>(blocks, 65536)),
+                       dim3(kBlock), 0, s, phi_c, nx, ny, nz, phi);
 }
 
 void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first,

@@ -47,6 +47,10 @@ def test_default_options():
     ({"nu1": 0, "nu2": 0}, (8, 8, 8), 0.1),
     ({}, (100, 100, 100), 0.01),          # multigrid: coarsest 25^3 > 512
     ({"limiter": "larsen", "larsen_n": 0.0}, (8, 8, 8), 0.1),
+    ({"nested_tol": -1.0}, (8, 8, 8), 0.1),
+    ({"nested_tol": 1e-3}, (5, 8, 8), 0.1),            # grid sequencing needs even axes
+    ({"nested_tol": 1e-3, "method": "rbsor"}, (8, 8, 8), 0.1),
+    ({"nested_tol": 1e-3, "anisotropy_g": 0.5}, (8, 8, 8), 0.1),
 ])
 def test_create_rejects_invalid_arguments(kw, dims, h):
     o = F.fld_default_options(**kw)
@@ -88,3 +92,10 @@ def test_render_rejects_invalid_arguments():
     assert L.fld_render(None, 1, 1, 1, 0.0, 4, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
     assert L.fld_render(1, 1, 1, 1, -1.0, 4, 4, 4, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
     assert L.fld_render(1, 1, 1, 1, 0.0, 4, 4, 0, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
+
+
+def test_batch_rejects_grid_sequencing():
+    o = F.fld_default_options(nested_tol=1e-3, precision="mixed")
+    with pytest.raises(F.FldError) as ei:
+        F.fld_batch_create(o, [(16, 16, 16)], [1.0 / 16], 1)
+    assert ei.value.status == F.FLD_ERR_INVALID_ARGUMENT

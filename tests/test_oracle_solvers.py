@@ -330,3 +330,24 @@ def test_alg1_converges_over_a_range_of_sor_factors(oracle_mod):
         assert r.status == "converged" and r.rel <= 1e-6, omega
         its[omega] = r.iterations
     assert its[1.4] < its[1.0]
+
+
+def test_grid_sequencing_problem_and_fixed_point(oracle_mod):
+    # Grid sequencing (our design): the 2:1 coarse medium averages 8 children.
+    # It conserves the total emission and absorption (sum over cells times
+    # cell volume), maps a homogeneous medium onto itself, and a solve started
+    # from the prolongated coarse fluence lands on the plain solve's fixed point.
+    st, al, Q, h = media.config("cloud128", n=32)
+    prob = oracle_mod.setup(st, al, Q, h)
+    c = oracle_mod.nested_problem(prob)
+    assert c.shape == (16, 16, 16) and c.params.h == 2 * h
+    for fine, coarse in ((prob.j, c.j), (prob.sig_a, c.sig_a)):
+        assert abs(coarse.sum() * (2 * h) ** 3 - fine.sum() * h ** 3) <= 1e-12 * fine.sum() * h ** 3
+    st1, al1, Q1, h1 = media.point_source(16, sigma_t=7.0, albedo=0.8)
+    p1 = oracle_mod.nested_problem(oracle_mod.setup(st1, al1, np.full_like(Q1, 2.0), h1))
+    np.testing.assert_allclose(p1.sig_hat, 7.0, rtol=1e-15)
+    np.testing.assert_allclose(p1.sig_a, 0.2 * 7.0, rtol=1e-14)
+    plain = oracle_mod.solve(prob, method="mg", tol=1e-10, max_iters=3000)
+    nest = oracle_mod.solve(prob, method="mg", tol=1e-10, max_iters=3000, nested_tol=1e-3)
+    assert nest.status == "converged" and nest.nested_iterations > 0
+    assert np.linalg.norm(nest.phi - plain.phi) <= 1e-8 * np.linalg.norm(plain.phi)
