@@ -89,8 +89,10 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
          probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
-         quick: bool = False, refine: bool = False) -> dict:
-    """Tune one grid/medium; stores and returns the cache entry."""
+         quick: bool = False, refine: bool = False, schedules=None, scales=None) -> dict:
+    """Tune one grid/medium; stores and returns the cache entry.  ``schedules``
+    ((nu1, nu2, omega_s, restart_growth) tuples) and ``scales`` replace the
+    default candidate lists (for grids whose full search is too long)."""
     import torch
 
     import paper_1403_8105_amd as F
@@ -153,13 +155,13 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     elif quick:
         best = run(*DEFAULT_SCHEDULE, 1.0)
     else:
-        for nu1, nu2, ws in SCHEDULES:
-            for gr in GROWTHS:
-                best = better(run(nu1, nu2, ws, gr, 1.0), best)
+        cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
+        for nu1, nu2, ws, gr in cands:
+            best = better(run(nu1, nu2, ws, gr, (scales or SCALES)[0]), best)
     if best is None:
         raise RuntimeError("autotune: no schedule reached the tolerance")
     if not old:
-        for sc in SCALES[1:]:
+        for sc in (scales or SCALES)[1:]:
             best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
                               sc), best)
     if even:
@@ -200,6 +202,11 @@ def main(argv=None):
     ap.add_argument("--max-iters", type=int, default=5000)
     ap.add_argument("--refine", action="store_true",
                     help="start from the cached entry; try only grid sequencing")
+    ap.add_argument("--schedules", default=None,
+                    help="candidate schedules 'nu1,nu2,omega_s,growth;...' (default: all)")
+    ap.add_argument("--scales", default=None,
+                    help="correction factors 'first,second,...'; the first goes with the "
+                         "schedule search (default 1.0,1.2,1.4,1.6,1.8)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from synth import media
@@ -207,7 +214,10 @@ def main(argv=None):
     st, al, Q, h = media.config(args.workload, n=args.n)
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
-                 max_iters=args.max_iters, refine=args.refine)
+                 max_iters=args.max_iters, refine=args.refine,
+                 schedules=[tuple(float(v) if i >= 2 else int(v) for i, v in enumerate(c.split(",")))
+                            for c in args.schedules.split(";")] if args.schedules else None,
+                 scales=[float(v) for v in args.scales.split(",")] if args.scales else None)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"]}), flush=True)
 
