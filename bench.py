@@ -475,8 +475,10 @@ def run_batch(args):
     dims = [(v["n"],) * 3 for v in vols]
     shapes = [d for d in dims for _ in range(3)]
     voxels = sum(a * b * c for a, b, c in dims)
-    # the batch has no tuner entry of its own: default launch shapes and schedule
-    tuned = {}
+    # the batch's own autotuner entry (schedule only; default launch shapes)
+    from paper_1403_8105_amd.autotune import batch_options
+    tuned = {} if args.no_tuned else batch_options("mixed", "lp")
+    log(f"bench: batch options from the autotuner cache: {tuned or 'none (defaults)'}")
     o = F.fld_default_options(precision="mixed", tol=1e-6, max_iters=args.max_iters, **tuned)
     b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
     for q, v in enumerate(vols):

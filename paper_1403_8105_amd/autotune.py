@@ -21,7 +21,8 @@ The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
 limiter), in ``tuned.json`` beside this file unless another path is given.
 ``Solver``-level callers pass ``tuned_options(...)`` as keyword options.
 
-Command line (tunes the synthetic cloud workload of ``synth.media``)::
+Command line (tunes the synthetic cloud workload of ``synth.media``; with
+``--workload batch`` the 16-volume x 3-channel batch, schedules only)::
 
     python -m paper_1403_8105_amd.autotune --workload cloud256 --precision mixed
 """
@@ -189,6 +190,79 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     return entry
 
 
+BATCH_KEY = "batch16x3"   # grid part of the cache key of the batched cloud workload
+
+
+def batch_options(precision: str = "mixed", limiter: str = "lp", arch: str | None = None,
+                  path: str = CACHE) -> dict:
+    """Cached options of the batched workload, or {} when it was never tuned."""
+    arch = arch or device_arch()
+    entry = load_cache(path).get(f"{arch}|{BATCH_KEY}|{precision}|{limiter}")
+    return dict(entry["options"]) if entry else {}
+
+
+def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
+               max_iters: int = 5000, path: str | None = CACHE, log=print, schedules=None,
+               scales=None) -> dict:
+    """Schedule search on the batched workload (``synth.media.batch_config``: 16
+    cloud volumes x 3 colour channels): every candidate is one whole batched
+    solve to the tolerance, default launch shapes; the shortest wins."""
+    import paper_1403_8105_amd as F
+    from synth import media
+
+    vols = media.batch_config()
+    dims = [(v["n"],) * 3 for v in vols]
+    shapes = [d for d in dims for _ in range(3)]
+    allow = (F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED)
+    results = []
+
+    def run(nu1, nu2, ws, gr, sc):
+        o = F.fld_default_options(precision=precision, limiter=limiter, tol=tol,
+                                  max_iters=max_iters, nu1=nu1, nu2=nu2, omega_s=ws,
+                                  restart_growth=gr, corr_scale=sc)
+        b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
+        try:
+            for q, v in enumerate(vols):
+                F.fld_batch_set_volume(b, q, v["sigma_t"], v["albedo"], v["Q"])
+            t0 = time.perf_counter()
+            _, its, rep = F.fld_batch_solve(b, shapes, allow=allow, want_phi=False)
+            ms = (time.perf_counter() - t0) * 1e3
+        finally:
+            F.fld_batch_destroy(b)
+        ok = rep["status"] == F.FLD_OK
+        results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
+                        "corr_scale": sc, "ms": ms, "iterations_max": int(its.max()),
+                        "converged": ok})
+        log(f"autotune batch: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} "
+            f"corr_scale={sc}: iterations {its.min()}..{its.max()}, {ms:.0f} ms"
+            f"{'' if ok else ' (not converged)'}")
+        return results[-1] if ok else None
+
+    def better(a, b):
+        return a if b is None or (a is not None and a["ms"] < b["ms"]) else b
+
+    scs = scales or SCALES
+    cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
+    best = None
+    for nu1, nu2, ws, gr in cands:
+        best = better(run(nu1, nu2, ws, gr, scs[0]), best)
+    if best is None:
+        raise RuntimeError("autotune batch: no schedule reached the tolerance")
+    for sc in scs[1:]:
+        best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"], sc),
+                      best)
+    entry = {"options": {k: best[k] for k in ("nu1", "nu2", "omega_s", "restart_growth",
+                                              "corr_scale")},
+             "tol": tol, "ms_to_tol": best["ms"], "iterations_max": best["iterations_max"],
+             "schedules": results}
+    if path:
+        cache = load_cache(path)
+        cache[f"{device_arch()}|{BATCH_KEY}|{precision}|{limiter}"] = entry
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return entry
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--workload", default="cloud256")
@@ -211,13 +285,22 @@ def main(argv=None):
     sys.path.insert(0, os.path.dirname(HERE))
     from synth import media
 
+    schedules = ([tuple(float(v) if i >= 2 else int(v) for i, v in enumerate(c.split(",")))
+                  for c in args.schedules.split(";")] if args.schedules else None)
+    scales = [float(v) for v in args.scales.split(",")] if args.scales else None
+    if args.workload == "batch":
+        entry = tune_batch(precision=args.precision, limiter=args.limiter, tol=args.tol,
+                           max_iters=args.max_iters, path=args.out,
+                           log=lambda m: print(m, flush=True), schedules=schedules,
+                           scales=scales)
+        print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"]}),
+              flush=True)
+        return
     st, al, Q, h = media.config(args.workload, n=args.n)
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
-                 max_iters=args.max_iters, refine=args.refine,
-                 schedules=[tuple(float(v) if i >= 2 else int(v) for i, v in enumerate(c.split(",")))
-                            for c in args.schedules.split(";")] if args.schedules else None,
-                 scales=[float(v) for v in args.scales.split(",")] if args.scales else None)
+                 max_iters=args.max_iters, refine=args.refine, schedules=schedules,
+                 scales=scales)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"]}), flush=True)
 
