@@ -134,8 +134,9 @@ typedef struct fld_options {
                              this relative residual, and start from its fluence, constant
                              over each 2x2x2 block.  Needs
                              every axis even and anisotropy_g = 0; set up by fld_set_medium
-                             in a second, coarse context (1/8 of the memory); single-volume
-                             contexts only.  0 disables (default)                           */
+                             (fld_batch_set_volume) in a second, coarse context (batch), 1/8
+                             of the memory.  In a batch, a problem whose coarse solve
+                             diverged starts from the paper's state.  0 disables (default)  */
 } fld_options;
 
 typedef struct fld_report {

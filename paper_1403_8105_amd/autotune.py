@@ -206,7 +206,8 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
                scales=None) -> dict:
     """Schedule search on the batched workload (``synth.media.batch_config``: 16
     cloud volumes x 3 colour channels): every candidate is one whole batched
-    solve to the tolerance, default launch shapes; the shortest wins."""
+    solve to the tolerance, default launch shapes; the shortest wins.  Grid
+    sequencing (``nested_tol``) is tried last for the winner."""
     import paper_1403_8105_amd as F
     from synth import media
 
@@ -216,10 +217,10 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     allow = (F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED)
     results = []
 
-    def run(nu1, nu2, ws, gr, sc):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0):
         o = F.fld_default_options(precision=precision, limiter=limiter, tol=tol,
                                   max_iters=max_iters, nu1=nu1, nu2=nu2, omega_s=ws,
-                                  restart_growth=gr, corr_scale=sc)
+                                  restart_growth=gr, corr_scale=sc, nested_tol=nt)
         b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
         try:
             for q, v in enumerate(vols):
@@ -231,10 +232,11 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
             F.fld_batch_destroy(b)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "ms": ms, "iterations_max": int(its.max()),
-                        "converged": ok})
+                        "corr_scale": sc, "nested_tol": nt, "ms": ms,
+                        "iterations_max": int(its.max()), "converged": ok})
         log(f"autotune batch: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} "
-            f"corr_scale={sc}: iterations {its.min()}..{its.max()}, {ms:.0f} ms"
+            f"corr_scale={sc} nested_tol={nt}: iterations {its.min()}..{its.max()} "
+            f"(+{rep.get('nested_iterations', 0)} coarse), {ms:.0f} ms"
             f"{'' if ok else ' (not converged)'}")
         return results[-1] if ok else None
 
@@ -251,8 +253,13 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     for sc in scs[1:]:
         best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"], sc),
                       best)
-    entry = {"options": {k: best[k] for k in ("nu1", "nu2", "omega_s", "restart_growth",
-                                              "corr_scale")},
+    if all(n % 2 == 0 for d in dims for n in d):
+        for nt in NESTED:
+            best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
+                              best["corr_scale"], nt), best)
+    keys = ("nu1", "nu2", "omega_s", "restart_growth", "corr_scale") + \
+        (("nested_tol",) if best["nested_tol"] else ())
+    entry = {"options": {k: best[k] for k in keys},
              "tol": tol, "ms_to_tol": best["ms"], "iterations_max": best["iterations_max"],
              "schedules": results}
     if path:

@@ -1164,6 +1164,8 @@ struct fld_batch {
     fld_engine_impl eng;
     int nvol = 0, nchan = 0;
     std::vector<int> has_medium;
+    fld_batch *nested = nullptr;   // grid sequencing: the 2:1 coarser batch
+    ~fld_batch();
 };
 
 namespace {
@@ -1315,12 +1317,44 @@ fld_status fld_default_options(fld_options *o)
 
 static thread_local std::string g_create_err;
 
+// Options of the 2:1 coarser problem of grid sequencing: the same physics and
+// precision, default launch shapes and schedule, solved to nested_tol (at most
+// 10000 iterations, not the fine cap, so chunked solves stay nested) without
+// timing.
+static fld_options nested_options(const fld_options *o)
+{
+    fld_options co;
+    fld_default_options(&co);
+    co.limiter = o->limiter;
+    co.larsen_n = o->larsen_n;
+    co.eps = o->eps;
+    co.sigma_eps = o->sigma_eps;
+    co.phi_b = o->phi_b;
+    co.boundary_d = o->boundary_d;
+    co.precision = o->precision;
+    co.max_coarsest = o->max_coarsest;
+    co.max_iters = 10000;
+    co.tol = o->nested_tol;
+    co.device = o->device;
+    co.stream = o->stream;
+    co.deflate_tau = o->deflate_tau;
+    co.graph = o->graph;
+    co.colour_split = o->colour_split;
+    return co;
+}
+
 fld_context::~fld_context()
 {
     if (nested)
         delete nested;
     if (d_nested_medium)
         hipFree(d_nested_medium);
+}
+
+fld_batch::~fld_batch()
+{
+    if (nested)
+        delete nested;
 }
 
 fld_status fld_create(const fld_options *o, int nx, int ny, int nz, double h, fld_context **out)
@@ -1351,25 +1385,7 @@ fld_status fld_create(const fld_options *o, int nx, int ny, int nz, double h, fl
         return s;
     }
     if (o->nested_tol > 0.0) {
-        // the coarse problem: same physics and precision, default launch
-        // shapes and schedule, solved to nested_tol without timing
-        fld_options co;
-        fld_default_options(&co);
-        co.limiter = o->limiter;
-        co.larsen_n = o->larsen_n;
-        co.eps = o->eps;
-        co.sigma_eps = o->sigma_eps;
-        co.phi_b = o->phi_b;
-        co.boundary_d = o->boundary_d;
-        co.precision = o->precision;
-        co.max_coarsest = o->max_coarsest;
-        co.max_iters = 10000;              // not the fine cap: chunked solves stay nested
-        co.tol = o->nested_tol;
-        co.device = o->device;
-        co.stream = o->stream;
-        co.deflate_tau = o->deflate_tau;
-        co.graph = o->graph;
-        co.colour_split = o->colour_split;
+        const fld_options co = nested_options(o);
         s = fld_create(&co, nx / 2, ny / 2, nz / 2, 2.0 * h, &c->nested);
         if (s == FLD_OK) {
             const size_t nc = (size_t)(nx / 2) * (ny / 2) * (nz / 2);
@@ -1682,10 +1698,11 @@ fld_status fld_batch_create(const fld_options *o, int nvol, const int *dims3, co
         err = "batched solves use the multigrid method";
         s = FLD_ERR_INVALID_ARGUMENT;
     }
-    if (s == FLD_OK && o->nested_tol > 0.0) {
-        err = "batch: grid sequencing (nested_tol) is for single-volume contexts";
-        s = FLD_ERR_INVALID_ARGUMENT;
-    }
+    for (int v = 0; s == FLD_OK && o->nested_tol > 0.0 && v < nvol; ++v)
+        if ((dims3[3 * v] | dims3[3 * v + 1] | dims3[3 * v + 2]) & 1) {
+            err = "nested_tol needs every axis of every volume even";
+            s = FLD_ERR_INVALID_ARGUMENT;
+        }
     if (s == FLD_OK && o->anisotropy_g != 0.0 && nchan > 1) {
         // the reduced extinction depends on each channel's albedo, while the
         // channels of a volume share one extinction field
@@ -1710,6 +1727,22 @@ fld_status fld_batch_create(const fld_options *o, int nvol, const int *dims3, co
     b->nvol = nvol;
     b->nchan = nchan;
     b->has_medium.assign(nvol, 0);
+    if (o->nested_tol > 0.0) {
+        const fld_options co = nested_options(o);
+        std::vector<int> cd(3 * (size_t)nvol);
+        std::vector<double> ch(nvol);
+        for (int v = 0; v < nvol; ++v) {
+            for (int a = 0; a < 3; ++a)
+                cd[3 * v + a] = dims3[3 * v + a] / 2;
+            ch[v] = 2.0 * h[v];
+        }
+        s = fld_batch_create(&co, nvol, cd.data(), ch.data(), nchan, &b->nested);
+        if (s != FLD_OK) {
+            g_create_err = "grid sequencing: " + g_create_err;
+            delete b;
+            return s;
+        }
+    }
     *out = b;
     return FLD_OK;
 }
@@ -1747,6 +1780,46 @@ fld_status fld_batch_set_volume(fld_batch *b, int v, const double *sigma_t,
     hipFree(dst); hipFree(dal); hipFree(dq);
     if (s != FLD_OK)
         return s;
+    if (b->nested) {
+        // the coarse volume: sigma_t (shared) and each channel's albedo and Q,
+        // averaged from the finest set-up fields of every channel
+        const Vol &V = E.vols[v];
+        const size_t nc = (size_t)(V.nx / 2) * (V.ny / 2) * (V.nz / 2);
+        double *dc = nullptr;
+        if (hipMalloc(&dc, 3 * 8 * nc) != hipSuccess)
+            return E.fail(FLD_ERR_OUT_OF_MEMORY, "grid sequencing: staging allocation failed");
+        std::vector<double> cst(nc);
+        std::vector<std::vector<double>> cal(b->nchan, std::vector<double>(nc)),
+            cq(b->nchan, std::vector<double>(nc));
+        hipError_t e = hipSuccess;
+        for (int ch = 0; ch < b->nchan && e == hipSuccess; ++ch) {
+            const Fine &f = E.probs[v * b->nchan + ch].fine;
+            launch_nested_coarsen(E.stream, f.sig_hat, f.sa64, f.j, V.nx, V.ny, V.nz, dc, dc + nc,
+                                  dc + 2 * nc);
+            e = hipGetLastError();
+            if (e == hipSuccess && ch == 0)
+                e = hipMemcpyAsync(cst.data(), dc, 8 * nc, hipMemcpyDeviceToHost, E.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(cal[ch].data(), dc + nc, 8 * nc, hipMemcpyDeviceToHost,
+                                   E.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(cq[ch].data(), dc + 2 * nc, 8 * nc, hipMemcpyDeviceToHost,
+                                   E.stream);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(E.stream);
+        }
+        hipFree(dc);
+        if (e != hipSuccess)
+            return E.hip_fail(e, "grid sequencing: coarse medium");
+        std::vector<const double *> pal(b->nchan), pq(b->nchan);
+        for (int ch = 0; ch < b->nchan; ++ch) {
+            pal[ch] = cal[ch].data();
+            pq[ch] = cq[ch].data();
+        }
+        s = fld_batch_set_volume(b->nested, v, cst.data(), pal.data(), pq.data());
+        if (s != FLD_OK)
+            return E.fail(s, "grid sequencing: coarse volume: %s", b->nested->eng.err.c_str());
+    }
     b->has_medium[v] = 1;
     for (int q = 0; q < b->nvol; ++q)
         if (!b->has_medium[q])
@@ -1764,9 +1837,38 @@ fld_status fld_batch_solve(fld_batch *b, double *const *phi_out, int *iters_out,
             return E.fail(FLD_ERR_STATE, "volume %d has no medium", q);
     auto t0 = std::chrono::steady_clock::now();
     double updates = 0.0;
-    fld_status s = E.solve_mg(0, &updates);
+    int start = 0, nested_its = 0;
+    if (b->nested) {
+        // grid sequencing: solve the coarse batch, start every problem from
+        // its coarse fluence (the paper's state where the coarse one diverged)
+        fld_report cr;
+        std::memset(&cr, 0, sizeof cr);
+        cr.struct_size = sizeof cr;
+        fld_status cs = fld_batch_solve(b->nested, nullptr, nullptr, &cr);
+        if (cs != FLD_OK && cs != FLD_ERR_NOT_CONVERGED && cs != FLD_ERR_DIVERGED)
+            return E.fail(cs, "grid sequencing: coarse solve: %s", b->nested->eng.err.c_str());
+        nested_its = cr.iterations;
+        updates += cr.voxel_updates;
+        const auto &CE = b->nested->eng;
+        for (int p = 0; p < E.nprob; ++p) {
+            const Vol &V = E.vols[E.probs[p].vol];
+            if (CE.probs[p].status != FLD_ERR_DIVERGED)
+                launch_nested_prolong(E.stream, CE.current_phi(p), V.nx, V.ny, V.nz,
+                                      E.probs[p].fine.phi[0]);
+            else
+                launch_init_phi(E.stream, E.d_fines, E.fine_tasks.d + E.fine_range[p],
+                                E.fine_range[p + 1] - E.fine_range[p], E.d_scal, 0, E.mixed);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return E.hip_fail(e, "grid sequencing: prolong launch");
+        start = 1;
+    }
+    double fine_updates = 0.0;
+    fld_status s = E.solve_mg(start, &fine_updates);
     if (s != FLD_OK)
         return s;
+    updates += fine_updates;
     E.solved_once = true;
     if (phi_out)
         for (int p = 0; p < E.nprob; ++p)
@@ -1792,6 +1894,8 @@ fld_status fld_batch_solve(fld_batch *b, double *const *phi_out, int *iters_out,
             status = E.probs[p].status;
     }
     fill_report(rep, E, worst, status, ms, updates, NAN);
+    if (rep && rep->struct_size == sizeof(fld_report))
+        rep->nested_iterations = nested_its;
     return (fld_status)status;
 }
 

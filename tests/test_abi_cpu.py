@@ -94,8 +94,8 @@ def test_render_rejects_invalid_arguments():
     assert L.fld_render(1, 1, 1, 1, 0.0, 4, 4, 0, 0.25, 1, None) == F.FLD_ERR_INVALID_ARGUMENT
 
 
-def test_batch_rejects_grid_sequencing():
+def test_batch_grid_sequencing_needs_even_axes():
     o = F.fld_default_options(nested_tol=1e-3, precision="mixed")
     with pytest.raises(F.FldError) as ei:
-        F.fld_batch_create(o, [(16, 16, 16)], [1.0 / 16], 1)
+        F.fld_batch_create(o, [(16, 16, 16), (10, 8, 5)], [1.0 / 16, 0.1], 1)
     assert ei.value.status == F.FLD_ERR_INVALID_ARGUMENT

@@ -64,3 +64,29 @@ def test_nested_is_skipped_with_a_start_state():
     ref = oracle.solve(oracle.setup(st, al, Q, h), method="mg", phi=phi0, tol=0.0, max_iters=3)
     assert rep["iterations"] == ref.iterations == 3
     assert rel_l2(phi, ref.phi) <= 1e-10
+
+
+def test_nested_batch_equals_individual_nested_solves():
+    # the coarse batch and the coarse context of a single solve compute the
+    # same bits, and so do the fine solves started from their fluence
+    vols = media.batch_config(nvol=3, size_scale=0.25, seed=3)
+    dims = [(v["n"],) * 3 for v in vols]
+    o = F.fld_default_options(precision="mixed", tol=1e-6, max_iters=3000, nested_tol=1e-2)
+    b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
+    try:
+        for i, v in enumerate(vols):
+            F.fld_batch_set_volume(b, i, v["sigma_t"], v["albedo"], v["Q"])
+        shapes = [d for d in dims for _ in range(3)]
+        outs, iters, rep = F.fld_batch_solve(b, shapes)
+    finally:
+        F.fld_batch_destroy(b)
+    assert rep["status"] == F.FLD_OK and rep["nested_iterations"] > 0
+    q = 0
+    for v in vols:
+        for c in range(3):
+            phi, r = solve_gpu(v["sigma_t"], v["albedo"][c], v["Q"][c], v["h"],
+                               precision="mixed", tol=1e-6, max_iters=3000, nested_tol=1e-2)
+            assert r["nested_iterations"] > 0
+            assert r["iterations"] == iters[q]
+            np.testing.assert_array_equal(outs[q], phi)
+            q += 1
