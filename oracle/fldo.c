@@ -20,7 +20,33 @@
  * eps*h (the paper's initial D, never updated on the boundary) or, in mirror
  * mode, the coefficient of the voxel inside.
  *
- * Parity status of each function is stated at the function.
+ * What pins each part to something other than itself (tests/test_oracle_*.py):
+ *   limiters (fldo_limiter*)       Table 2 closed forms with mpmath-derived
+ *                                  constants; R -> 0 and R -> inf limits; F <= 1/R;
+ *                                  the small-R branch of LP; CDA constant
+ *   set-up, Knudsen number, limiter exact gradients of linear fields; the guard
+ *   pass (fldo_setup, fldo_knudsen, branches worked by hand; |E| <= phi after a
+ *   fldo_limiter_pass)             pass (the flux-limiting bound of Sec. 4)
+ *   residual (fldo_residual,       an independent scipy assembly of the same
+ *   fldo_nonlinear_residual)       system; symmetric M-matrix; exact discrete power
+ *                                  balance; bit-exact homogeneity in Q; axis
+ *                                  permutation symmetry
+ *   Algorithm 1 (fldo_alg1_*,      CDA equals a sparse direct solve; FLD equals a
+ *   solve_alg1)                    brute-force Picard fixed point on <= 8^3; the
+ *                                  CDA point source follows the closed-form
+ *                                  Green's function, with second-order refinement;
+ *                                  the SOR rate equals Young's formula from the
+ *                                  Jacobi spectral radius
+ *   multigrid (fldo_mg_levels,     Galerkin identity A_1 = P^T A_0 P / 8 in numpy;
+ *   levels, smoother, transfers,   a single-level V-cycle is exact; Cholesky vs
+ *   Cholesky, solve_mg)            numpy; the multigrid solve reaches the sparse
+ *                                  direct / brute-force fixed points and the one of
+ *                                  Algorithm 1; power balance at convergence
+ *   clusters, deflation, restarts  scipy connected components; deflation and
+ *                                  direction restarts keep the fixed point
+ *   reduced extinction (aniso_g)   the CDA Green's function with D = 1/(3 sigma_t')
+ *   light baking, render           closed forms of a homogeneous column; vacuum;
+ *                                  linearity; product form of the transmittance
  */
 #include <math.h>
 #include <stdlib.h>
