@@ -329,8 +329,8 @@ def test_batch_mixing_split_and_natural_volumes():
 
 @pytest.mark.parametrize("nu1,nu2,omega_s,growth,scale", [
     (1, 1, 1.0, 2.0, 1.0), (2, 1, 1.0, 2.0, 1.0), (1, 2, 1.0, 2.0, 1.0), (3, 3, 1.0, 10.0, 1.0),
-    (2, 2, 1.15, 2.0, 1.0), (3, 3, 1.15, 10.0, 1.6), (2, 2, 1.0, 0.0, 1.4),
-    (3, 3, 1.15, 2.0, 1.8), (4, 4, 1.15, 2.0, 2.0), (3, 3, 1.3, 10.0, 1.8)])
+    (2, 2, 1.15, 2.0, 1.4), (3, 3, 1.15, 10.0, 1.6), (2, 2, 1.0, 0.0, 1.4),
+    (3, 3, 1.15, 2.0, 2.0), (4, 4, 1.15, 2.0, 2.0), (3, 3, 1.3, 10.0, 1.8)])
 def test_mg_schedules_iterate_parity(nu1, nu2, omega_s, growth, scale):
     # every schedule, restart factor and correction factor the autotuner may
     # pick (and every cached one) follows the oracle
