@@ -85,29 +85,62 @@ def counter_traffic():
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(st, al, Q, h, budget_s=20.0):
-    """Oracle (plain FP64 C) on a bounded sample: a few outer multigrid
-    iterations of the same 256^3 solve; voxel-updates/s on the same definition."""
+def host_cpu():
+    """Model name, physical cores and usable logical CPUs of this host."""
+    model, cores = None, set()
+    phys = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    cores.add((phys, val))
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "physical_cores": len(cores) or None, "usable_cpus": usable}
+
+
+def cpu_baseline(st, al, Q, h, schedule, gpu_iterations, budget_s=20.0):
+    """Oracle (plain FP64 C) on a bounded sample: outer multigrid iterations
+    of the same solve with the GPU solve's schedule, voxel-updates/s on the
+    same definition, and the time to the tolerance that rate implies for the
+    GPU's iteration count (an extrapolation, labelled as such)."""
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    kw = {k: schedule[k] for k in ("nu1", "nu2", "omega_s", "restart_growth", "corr_scale")
+          if k in schedule}
+    nu = kw.get("nu1", 2) + kw.get("nu2", 2)
     t0 = time.perf_counter()
     prob = oracle.setup(st, al, Q, h)
     levels, _ = oracle.mg_levels(*st.shape)
-    per_it = sum(a * b * c for a, b, c in levels[:-1]) * 4.0   # V(2,2) point updates
+    per_it = sum(a * b * c for a, b, c in levels[:-1]) * float(nu)   # point updates
     t1 = time.perf_counter()
-    oracle.solve(prob, method="mg", tol=0.0, max_iters=1)
+    oracle.solve(prob, method="mg", tol=0.0, max_iters=1, **kw)
     t_one = time.perf_counter() - t1
     its = max(1, min(40, int(budget_s / max(t_one, 1e-3))))
     t2 = time.perf_counter()
-    res = oracle.solve(prob, method="mg", tol=0.0, max_iters=its)
+    res = oracle.solve(prob, method="mg", tol=0.0, max_iters=its, **kw)
     dt = time.perf_counter() - t2
-    return {"value": per_it * res.iterations / dt, "unit": "voxel-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{res.iterations} outer multigrid iterations of the {st.shape[0]}^3 "
-                      f"cloud solve (FP64, OpenMP threads={threads}; the time includes the "
-                      f"limiter and residual passes of each iteration), {dt:.1f} s after "
-                      f"{t1 - t0:.1f} s set-up"}
+    out = {"value": per_it * res.iterations / dt, "unit": "voxel-updates/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{res.iterations} outer multigrid iterations of the {st.shape[0]}^3 "
+                     f"cloud solve with the GPU solve's schedule {kw or '(defaults)'} "
+                     f"(FP64, OpenMP threads={threads}; the time includes the limiter and "
+                     f"residual passes of each iteration), {dt:.1f} s after "
+                     f"{t1 - t0:.1f} s set-up",
+           "s_per_outer_iteration": dt / res.iterations,
+           "est_time_to_tol_s": dt / res.iterations * gpu_iterations,
+           "est_note": f"s_per_outer_iteration x the {gpu_iterations} outer iterations of the "
+                       f"GPU solve (extrapolated, not run)"}
+    out.update(host_cpu())
+    return out
 
 
 def copy_calibration(nbytes, reps=5):
@@ -155,8 +188,10 @@ def main():
                              "convergence"])
     ap.add_argument("--chunk", type=int, default=0,
                     help="outer iterations per call (0: one call); later calls resume")
-    ap.add_argument("--sequential", action="store_true",
+    ap.add_argument("--sequential", action=argparse.BooleanOptionalAction, default=True,
                     help="batch workload: also time the problems solved one at a time")
+    ap.add_argument("--err-tol", type=float, default=5e-11,
+                    help="tolerance of the FP64 reference solve for err_vs_fp64 (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -219,11 +254,17 @@ def main():
         log(f"bench: {prec} options from the autotuner cache ({tuned_from[prec]}): "
             f"{tuned[prec] or 'none (defaults)'}")
 
-    def make(precision, timing):
-        s = F.Solver(st.shape, h, precision=precision, tol=args.tol,
-                     max_iters=args.chunk or args.max_iters, timing=timing, stream=sp,
-                     **tuned[precision])
+    setup_ms = []
+
+    def make(precision, timing, tol=None, max_iters=None):
+        s = F.Solver(st.shape, h, precision=precision, tol=args.tol if tol is None else tol,
+                     max_iters=max_iters or args.chunk or args.max_iters, timing=timing,
+                     stream=sp, **tuned[precision])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
         s.set_medium_device(d_st.data_ptr(), d_al.data_ptr(), d_Q.data_ptr(), sp)
+        torch.cuda.synchronize()
+        setup_ms.append((time.perf_counter() - t) * 1e3)
         return s
 
     # HIP events cost a few microseconds per graph node, so one context with
@@ -287,6 +328,7 @@ def main():
     traffic = (counter_traffic() if args.workload == "cloud256" and args.precision == "mixed"
                and n == 256 else None)
     ok = all(r["status"] == 0 for r in reps)
+    phi_head = d_phi.clone()          # the last timed solve's fluence
     line = {
         "metric": ("voxel-updates/s + time to 1e-6 rel. residual (256^3 FLD); % HBM peak"
                    if args.workload == "cloud256" else
@@ -317,6 +359,11 @@ def main():
                    "grid": [n, n, n], "tol": args.tol, "precision": args.precision,
                    "tuned_options": tuned[args.precision],
                    "tuned_on_grid": tuned_from[args.precision]},
+        "setup_ms": setup_ms[0],
+        "setup_note": "fld_set_medium_device of the timed context (outside the timed region): "
+                      "validation copy of the medium to the host, set-up kernels, host cluster "
+                      "labelling and upload, coarse operators, and the 2:1 coarser context of "
+                      "grid sequencing when the schedule uses it",
         "timing": "per-kernel HIP events recorded in the last timed step only",
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -337,9 +384,40 @@ def main():
                             "final_rel": r64["rel"], "converged": r64["status"] == 0,
                             "mixed_speedup": t64 * 1e3 / ms_step}
         log(f"bench: fp64 {r64['iterations']} iterations, rel {r64['rel']:.2e}, {t64:.2f} s")
+        if args.err_tol > 0:
+            # error of the mixed fluence against the plain FP64 GPU solve at
+            # its residual floor (that path follows the oracle iterate by
+            # iterate, also at 256^3), and of a mixed solve to 1e-10
+            log(f"bench: FP64 GPU solve to {args.err_tol:g} as the error reference")
+            ref = make("fp64", 0, tol=args.err_tol, max_iters=20000)
+            rr = F.fld_solve_device(ref.ctx, d_phi.data_ptr(),
+                                    allow=(F.FLD_OK, F.FLD_ERR_NOT_CONVERGED))
+            ref.close()
+            phi_ref = d_phi.clone()
+            m10 = make(args.precision, 0, tol=1e-10, max_iters=20000)
+            t1 = time.perf_counter()
+            r10 = F.fld_solve_device(m10.ctx, d_phi.data_ptr(),
+                                     allow=(F.FLD_OK, F.FLD_ERR_NOT_CONVERGED))
+            torch.cuda.synchronize()
+            t10 = time.perf_counter() - t1
+            m10.close()
+            nref = torch.linalg.vector_norm(phi_ref).item()
+            line["err_vs_fp64"] = {
+                "reference": f"plain FP64 GPU solve of the same medium to rel "
+                             f"{rr['rel']:.2e} ({rr['iterations']} outer iterations; "
+                             f"{'converged' if rr['status'] == 0 else 'stopped at the cap'} "
+                             f"for tol {args.err_tol:g})",
+                "metric": "||phi - phi_ref||_2 / ||phi_ref||_2",
+                "mixed_at_tol": torch.linalg.vector_norm(phi_head - phi_ref).item() / nref,
+                "mixed_to_1e-10": torch.linalg.vector_norm(d_phi - phi_ref).item() / nref,
+                "mixed_to_1e-10_iterations": r10["iterations"],
+                "mixed_to_1e-10_rel": r10["rel"],
+                "mixed_to_1e-10_ms": t10 * 1e3}
+            log(f"bench: err_vs_fp64 {line['err_vs_fp64']}")
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        line["cpu_baseline"] = cpu_baseline(st, al, Q, h)
+        line["cpu_baseline"] = cpu_baseline(st, al, Q, h, tuned[args.precision],
+                                            reps[-1]["iterations"])
     print(json.dumps(line), flush=True)
 
 
@@ -520,6 +598,24 @@ def run_batch(args):
                                "mixed Picard multigrid, one batched solve to rel 1e-6",
                    "voxels": voxels, "problems": len(shapes), "tuned_options": tuned},
     }
+    if not args.no_fp64:
+        # the same batch in plain FP64 with the FP64 defaults (no batch entry
+        # is cached for it), one solve
+        log("bench: the batch in plain FP64")
+        o64 = F.fld_default_options(precision="fp64", tol=1e-6, max_iters=args.max_iters)
+        b64 = F.fld_batch_create(o64, dims, [v["h"] for v in vols], 3)
+        for q, v in enumerate(vols):
+            F.fld_batch_set_volume(b64, q, v["sigma_t"], v["albedo"], v["Q"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, its64, r64 = F.fld_batch_solve(b64, shapes, want_phi=False)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        F.fld_batch_destroy(b64)
+        line["fp64_gpu_batch"] = {"time_to_tol_ms": t64 * 1e3,
+                                  "converged": r64["status"] == 0,
+                                  "outer_iterations_min_max": [int(its64.min()), int(its64.max())],
+                                  "mixed_speedup": t64 / (dt / args.steps)}
     if args.sequential:
         log("bench: the same 48 problems one at a time")
         seq = 0.0

@@ -610,9 +610,11 @@ static void assemble_level(const mg_level *L, double d_ghost, int mirror, double
             }
 }
 
-/* V(nu1, nu2) cycle on levels[l..nlev-1] from a zero initial guess. */
+/* V(nu1, nu2) cycle on levels[l..nlev-1].  Every level starts from a zero
+ * correction, except the first when e_start is given: its smoothing then
+ * starts from e_start (the cluster deflation step). */
 static void vcycle(mg_level *lv, int l, int nlev, const fldo_solve_opts *o, double d_ghost,
-                   int mirror, const double *chol)
+                   int mirror, const double *chol, const double *e_start)
 {
     mg_level *L = &lv[l];
     long n = (long)L->nx * L->ny * L->nz;
@@ -625,14 +627,17 @@ static void vcycle(mg_level *lv, int l, int nlev, const fldo_solve_opts *o, doub
         free(rhs);
         return;
     }
-    memset(L->e, 0, sizeof(double) * n);
+    if (e_start)
+        memcpy(L->e, e_start, sizeof(double) * n);
+    else
+        memset(L->e, 0, sizeof(double) * n);
     for (int s = 0; s < o->nu1; ++s) {
         level_smooth_colour(L, d_ghost, mirror, 0, o->omega_s);
         level_smooth_colour(L, d_ghost, mirror, 1, o->omega_s);
     }
     level_residual(L, d_ghost, mirror, L->r);
     mean8(lv[l + 1].nx, lv[l + 1].ny, lv[l + 1].nz, L->ny, L->nz, L->r, lv[l + 1].b);
-    vcycle(lv, l + 1, nlev, o, d_ghost, mirror, chol);
+    vcycle(lv, l + 1, nlev, o, d_ghost, mirror, chol, NULL);
     prolong_add(&lv[l + 1], L, l == 0 ? o->corr_scale : 1.0);
     for (int s = 0; s < o->nu2; ++s) {
         level_smooth_colour(L, d_ghost, mirror, 1, o->omega_s);
@@ -716,7 +721,10 @@ static int hier_coarsen(mg_hier *H, int coarsen_sa, double d_ghost, int mirror)
 /* indicator functions is diagonal: d_c = sum_{p in c} sa_p + sum of the    */
 /* coefficients (/h^2) of faces leaving c.  One deflation step              */
 /* e1 = sum_c (sum_{p in c} r_p / d_c) 1_c precedes the V-cycle, which then */
-/* works on r - A e1.                                                       */
+/* works on r - A e1.  It does so by starting the finest smoothing from e1  */
+/* with right-hand side r: every step of the cycle is affine in the         */
+/* correction and the right-hand side, so this equals e1 plus a cycle from  */
+/* zero on r - A e1, without forming A e1.                                  */
 /* ------------------------------------------------------------------------ */
 
 static int uf_find(int *parent, int x)
@@ -854,7 +862,7 @@ int fldo_linear_vcycle(int nx, int ny, int nz, double h, double d_ghost, int mir
     memcpy(H.lv[0].b, b0, sizeof(double) * n);
     int rc = hier_coarsen(&H, 1, d_ghost, mirror);
     if (rc == 0) {
-        vcycle(H.lv, 0, nlev, o, d_ghost, mirror, H.chol);
+        vcycle(H.lv, 0, nlev, o, d_ghost, mirror, H.chol, NULL);
         memcpy(e0, H.lv[0].e, sizeof(double) * n);
     }
     hier_free(&H);
@@ -945,7 +953,8 @@ static int solve_alg1(const fldo_params *p, const fldo_solve_opts *o, const doub
  *   D^k = limiter pass on phi^k (every voxel), r^k = j - A(D^k) phi^k (FP64),
  *   stop when ||r^k||/||j|| <= tol;
  *   e^k = the preconditioner applied to r^k: cluster deflation e1, then one
- *   V-cycle for A(D^k) e = r^k - A(D^k) e1, e^k = e1 + e;
+ *   V-cycle for A(D^k) e = r^k whose finest smoothing starts from e1 (equal
+ *   to e1 plus a cycle from zero on r^k - A(D^k) e1);
  *   gamma_k = r^k.e^k; beta_k = max(0, (gamma_k - e^k.r^{k-1}) / gamma_{k-1})
  *   (Polak-Ribiere, restarted when negative; beta_0 = 0);
  *   p^k = e^k + beta_k p^{k-1};
@@ -994,20 +1003,14 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
         if (it >= o->max_iters) { status = FLDO_NOT_CONVERGED; break; }
         if (hier_coarsen(&H, first, d_ghost, p->mirror_d)) { status = FLDO_DIVERGED; break; }
         first = 0;
-        /* preconditioner: cluster deflation, then one V-cycle on the rest */
+        /* preconditioner: cluster deflation, then one V-cycle whose finest
+         * smoothing starts from the deflation step */
         if (K > 0) {
             cluster_diag(&H.lv[0], d_ghost, p->mirror_d, label, K, dcl);
             cluster_correction(n, label, K, dcl, r, scl, e1);
-            level_apply(&H.lv[0], d_ghost, p->mirror_d, e1, q);
-            for (long c = 0; c < n; ++c)
-                H.lv[0].b[c] = r[c] - q[c];
-        } else {
-            memcpy(H.lv[0].b, r, sizeof(double) * n);
         }
-        vcycle(H.lv, 0, nlev, o, d_ghost, p->mirror_d, H.chol);
-        if (K > 0)
-            for (long c = 0; c < n; ++c)
-                e[c] = e1[c] + e[c];
+        memcpy(H.lv[0].b, r, sizeof(double) * n);
+        vcycle(H.lv, 0, nlev, o, d_ghost, p->mirror_d, H.chol, K > 0 ? e1 : NULL);
         double theta;
         if (o->step_mode == 1 || o->step_mode == 2) {
             double gamma = 0.0, e_rprev = 0.0;

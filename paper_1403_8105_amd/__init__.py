@@ -57,6 +57,7 @@ class FldError(RuntimeError):
 
 
 _lib = None
+_lib_loaded_from = None
 EXPORTS = ["fld_default_options", "fld_create", "fld_set_medium", "fld_set_medium_device",
            "fld_solve", "fld_solve_device", "fld_solve_resume", "fld_residual",
            "fld_residual_device", "fld_destroy", "fld_status_string", "fld_last_error",
@@ -65,8 +66,16 @@ EXPORTS = ["fld_default_options", "fld_create", "fld_set_medium", "fld_set_mediu
 
 
 def lib():
-    """Load libfld.so (raises if it has not been built)."""
-    global _lib
+    """Load libfld.so (raises if it has not been built).
+
+    A process uses one build of the library: a context belongs to the copy
+    that created it, and handing it to a second copy (another path) would
+    run that copy's code on the first copy's objects.  Asking for another
+    path after the first load raises."""
+    global _lib, _lib_loaded_from
+    if _lib is not None and _lib_loaded_from != LIB_PATH:
+        raise RuntimeError(f"libfld.so is already loaded from {_lib_loaded_from}; "
+                           f"load {LIB_PATH} in another process")
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_1403_8105_amd/build.py")
@@ -101,7 +110,7 @@ def lib():
         L.fld_batch_destroy.restype = None
         L.fld_batch_last_error.argtypes = [vp]
         L.fld_batch_last_error.restype = C.c_char_p
-        _lib = L
+        _lib, _lib_loaded_from = L, LIB_PATH
     return _lib
 
 
@@ -309,6 +318,7 @@ class Solver:
 
     def __init__(self, shape, h, **options):
         self.shape = tuple(int(x) for x in shape)
+        self._L = lib()              # the copy of the library that owns the context
         self.opts = fld_default_options(**options)
         self.ctx = fld_create(self.opts, *self.shape, float(h))
 
@@ -329,7 +339,7 @@ class Solver:
 
     def close(self):
         if self.ctx:
-            fld_destroy(self.ctx)
+            self._L.fld_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

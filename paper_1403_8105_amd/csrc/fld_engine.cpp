@@ -74,7 +74,6 @@ struct fld_engine_impl {
 
     Fine *d_fines = nullptr;
     Grid *d_grids[2] = {nullptr, nullptr};
-    Grid *d_grids_defl = nullptr;   // level-0 right-hand side = deflated b1
     // cluster deflation (built when the media are set)
     bool defl_enabled = false, use_defl = false;
     int ncl_total = 0;
@@ -120,11 +119,18 @@ struct fld_engine_impl {
     double fine_cells = 0.0;       // sum of finest-level cells over problems
     bool capturing = false;
 
+    // Events are only ever created outside stream capture: the ones a graph
+    // records are made before its capture begins (reserve_graph_events) and
+    // handed out from graph_spare while it is captured.
     hipEvent_t next_event()
     {
         if (capturing) {
-            hipEvent_t e = nullptr;
-            note(hipEventCreate(&e), "hipEventCreate");
+            if (graph_spare.empty()) {
+                note(hipErrorInvalidValue, "graph timing events exhausted");
+                return nullptr;
+            }
+            hipEvent_t e = graph_spare.back();
+            graph_spare.pop_back();
             graph_events.push_back(e);
             return e;
         }
@@ -135,33 +141,31 @@ struct fld_engine_impl {
         }
         return ev_pool[ev_used++];
     }
-    // Under capture the record becomes an event node of the graph, re-recorded
-    // on every replay.
+    // Under capture the record becomes an event-record node of the graph
+    // (re-recorded on every replay); the runtime links it after the work
+    // captured so far.
     void record(hipEvent_t e)
     {
-        if (!capturing) {
-            note(hipEventRecord(e, stream), "hipEventRecord");
+        if (!e)
             return;
-        }
-        // insert an event-record node after the captured work so far and
-        // make it the dependency of what is captured next
-        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-        hipGraph_t g = nullptr;
-        const hipGraphNode_t *deps = nullptr;
-        size_t nd = 0;
-        hipError_t r = hipStreamGetCaptureInfo_v2(stream, &st, nullptr, &g, &deps, &nd);
-        if (r != hipSuccess || st != hipStreamCaptureStatusActive || !g) {
-            note(r != hipSuccess ? r : hipErrorIllegalState, "hipStreamGetCaptureInfo_v2");
+        note(hipEventRecordWithFlags(e, stream, capturing ? hipEventRecordExternal : 0),
+             "hipEventRecord");
+    }
+    // Timing events one captured outer iteration records: a pair around every
+    // finest-level half-sweep, the limiter, the residual and the direction pass.
+    void reserve_graph_events()
+    {
+        if (!opt.timing)
             return;
+        const size_t need = 2 * (size_t)(2 * (opt.nu1 + opt.nu2) + 3);
+        while (graph_spare.size() < need) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                note(hipErrorOutOfMemory, "hipEventCreate");
+                return;
+            }
+            graph_spare.push_back(e);
         }
-        hipGraphNode_t node = nullptr;
-        r = hipGraphAddEventRecordNode(&node, g, deps, nd, e);
-        if (r != hipSuccess) {
-            note(r, "hipGraphAddEventRecordNode");
-            return;
-        }
-        note(hipStreamUpdateCaptureDependencies(stream, &node, 1, hipStreamSetCaptureDependencies),
-             "hipStreamUpdateCaptureDependencies");
     }
     // First failure of a call whose status is not returned at once.
     hipError_t pending = hipSuccess;
@@ -187,6 +191,8 @@ struct fld_engine_impl {
             return;
         hipEvent_t b = next_event();
         record(b);
+        if (!a || !b)
+            return;
         // a graph's launches see the problems active when it is replayed
         timed_sink->push_back(
             Timed{a, b, cls, bytes_per_cell, capturing ? -1.0 : active_fine_cells()});
@@ -224,7 +230,7 @@ struct fld_engine_impl {
     // residual passes.
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     std::vector<Timed> graph_timed[2];
-    std::vector<hipEvent_t> graph_events;
+    std::vector<hipEvent_t> graph_events, graph_spare;
     bool graphs_ok = true;
 
     void drop_graphs()
@@ -238,6 +244,9 @@ struct fld_engine_impl {
         for (hipEvent_t e : graph_events)
             hipEventDestroy(e);
         graph_events.clear();
+        for (hipEvent_t e : graph_spare)
+            hipEventDestroy(e);
+        graph_spare.clear();
     }
 
     ~fld_engine_impl()
@@ -391,8 +400,6 @@ struct fld_engine_impl {
                 CK(dalloc(&f.e0, NS));
                 CK(dalloc(&f.p[0], NT));
                 CK(dalloc(&f.p[1], NT));
-                if (opt.deflate_tau > 0.0)
-                    CK(dalloc(&f.b1, NS));
                 if (mixed) {
                     CK(dalloc(&f.D0, NS));
                     CK(dalloc(&f.sa0, NS));
@@ -502,14 +509,6 @@ struct fld_engine_impl {
                "hipMemcpy grids");
         }
         defl_enabled = opt.deflate_tau > 0.0;
-        if (defl_enabled) {
-            std::vector<Grid> gd = grids[0];
-            for (int p = 0; p < nprob; ++p)
-                gd[probs[p].gid0].b = probs[p].fine.b1;
-            CK(dalloc(&d_grids_defl, sizeof(Grid) * ngrids));
-            HK(hipMemcpy(d_grids_defl, gd.data(), sizeof(Grid) * ngrids, hipMemcpyHostToDevice),
-               "hipMemcpy grids");
-        }
         // deep part: from the first level (below the finest) with at most
         // opt.deep_cells cells; levels above it use the work-list kernels
         std::vector<int> roots, coarsest;
@@ -831,14 +830,20 @@ struct fld_engine_impl {
         return c;
     }
 
-    // par: parity of the level-0 right-hand side buffer, -1: the deflated one
+    // par: parity of the level-0 right-hand side buffer.  With deflation the
+    // finest level starts from the cluster step e0 = alpha[label], every
+    // other level from zero.
     template <typename T>
     void vcycle(int par)
     {
-        Grid *G = par < 0 ? d_grids_defl : d_grids[par];
+        Grid *G = d_grids[par];
         for (int l = 0; l < max_levels; ++l) {
             if (mid[l].n) {
-                launch_zero<T>(stream, G, mid[l].d, mid[l].n, d_active);
+                if (l == 0 && use_defl)
+                    launch_defl_init(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active,
+                                     d_alpha, kmode);
+                else
+                    launch_zero<T>(stream, G, mid[l].d, mid[l].n, d_active);
                 for (int s = 0; s < opt.nu1; ++s) {
                     smooth<T>(G, l, 0);
                     smooth<T>(G, l, 1);
@@ -923,18 +928,16 @@ struct fld_engine_impl {
                                kmode);
             launch_defl_finish(stream, ncl_total, d_crange, d_cprob, d_cpd, d_cps, d_alpha,
                                d_active);
-            launch_defl_apply(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_alpha,
-                              kmode);
         }
         if (mixed) {
             coarsen<float>();
-            vcycle<float>(use_defl ? -1 : (k & 1));
+            vcycle<float>(k & 1);
         } else {
             coarsen<double>();
-            vcycle<double>(use_defl ? -1 : (k & 1));
+            vcycle<double>(k & 1);
         }
         launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_part[0],
-                         d_part[1], use_defl ? d_alpha : nullptr, kmode);
+                         d_part[1], kmode);
         launch_sum_partials(stream, N, d_fine_range, d_part[0], d_scal, S_GAMMA, d_active);
         launch_sum_partials(stream, N, d_fine_range, d_part[1], d_scal, S_SIGMA, d_active);
         launch_npcg_beta(stream, N, d_scal, d_active, k == 0 ? 1 : 0, opt.restart_growth);
@@ -953,6 +956,7 @@ struct fld_engine_impl {
     bool capture(int k)
     {
         const int par = k & 1;
+        reserve_graph_events();
         if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             (void)hipGetLastError();
             return false;
@@ -1596,8 +1600,14 @@ fld_status fld_solve_resume(fld_context *c, double *phi_out, fld_report *rep)
     return solve_impl(c, nullptr, false, phi_out, false, 1, rep);
 }
 
+// Nonlinear residual of phi (NULL: the context's current fluence), D
+// recomputed from phi for every voxel.  Without a workspace the temporaries
+// are allocated here and phi / r_out are host pointers unless dev.  With a
+// workspace (device memory of the caller) nothing is allocated: phi and
+// r_out are device pointers, phi is read in place, and the problem
+// descriptor is written by a kernel.
 static fld_status residual_impl(fld_context *c, const double *phi, bool dev, double *r_out,
-                                double *rel_out)
+                                double *rel_out, const ResidualWork *ws)
 {
     if (!c)
         return FLD_ERR_INVALID_ARGUMENT;
@@ -1608,6 +1618,31 @@ static fld_status residual_impl(fld_context *c, const double *phi, bool dev, dou
         return E.fail(FLD_ERR_INVALID_ARGUMENT, "rel_out is NULL");
     const long long n = E.vols[0].n;
     Fine f = E.probs[0].fine;
+    if (ws) {
+        if (n > ws->max_cells)
+            return E.fail(FLD_ERR_INVALID_ARGUMENT,
+                          "grid of %lld cells exceeds the workspace of %lld cells", n,
+                          ws->max_cells);
+        f.phi[0] = f.phi[1] = const_cast<double *>(phi ? phi : E.current_phi(0));
+        f.Dtmp = ws->D;
+        f.b0[0] = f.b0[1] = ws->b;
+        launch_put_fine(E.stream, f, ws->fine);
+        launch_limiter(E.stream, ws->fine, E.fine_tasks.d, E.fine_tasks.n, nullptr, E.d_scal, 0,
+                       0, 0, 0, 1, 0);
+        launch_residual(E.stream, ws->fine, E.fine_tasks.d, E.fine_tasks.n, nullptr, 0, 1, 0,
+                        r_out, E.d_part[0], 0);
+        launch_sum_partials(E.stream, 1, E.d_fine_range, E.d_part[0], E.d_scal, S_AUX, nullptr);
+        double sc[S_COUNT];
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sc, E.d_scal, sizeof sc, hipMemcpyDeviceToHost, E.stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(E.stream);
+        if (e != hipSuccess)
+            return E.hip_fail(e, "residual");
+        *rel_out = sc[S_JNORM] > 0.0 ? std::sqrt(sc[S_AUX]) / sc[S_JNORM] : 0.0;
+        return FLD_OK;
+    }
     double *tphi = nullptr, *tD = nullptr, *tr = nullptr;
     void *tb = nullptr;
     Fine *dfine = nullptr;
@@ -1648,13 +1683,13 @@ static fld_status residual_impl(fld_context *c, const double *phi, bool dev, dou
 
 fld_status fld_residual(fld_context *c, const double *phi, double *r_out, double *rel_out)
 {
-    return residual_impl(c, phi, false, r_out, rel_out);
+    return residual_impl(c, phi, false, r_out, rel_out, nullptr);
 }
 
 fld_status fld_residual_device(fld_context *c, const double *d_phi, double *d_r_out,
                                double *rel_out)
 {
-    return residual_impl(c, d_phi, true, d_r_out, rel_out);
+    return residual_impl(c, d_phi, true, d_r_out, rel_out, nullptr);
 }
 
 void fld_destroy(fld_context *c) { delete c; }
@@ -1909,3 +1944,15 @@ const char *fld_batch_last_error(const fld_batch *b)
 }
 
 }  // extern "C"
+
+namespace fld {
+
+fld_status residual_with_workspace(fld_context *c, const double *d_phi, double *d_r_out,
+                                   double *rel_out, const ResidualWork *ws)
+{
+    return residual_impl(c, d_phi, true, d_r_out, rel_out, ws);
+}
+
+int context_device(const fld_context *c) { return c ? c->eng.opt.device : -1; }
+
+}  // namespace fld

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/fld.h"
+
 namespace fld {
 
 constexpr int kBlock = 256;          // threads per block of the work-list kernels
@@ -44,7 +46,7 @@ struct Fine {
     long long n;
     double h, h2, dghost, eps, phi_b, larsen_n;
     int mirror, limiter, write_sighat;
-    int split;           // precision-T fields e0, b0, b1, D0, sa0 stored colour by colour in
+    int split;           // precision-T fields e0, b0, D0, sa0 stored colour by colour in
                          // blocks of 64 cells: cell c of colour q = (i+j+k)&1 at
                          // (c>>6)*64 + q*32 + ((c>>1)&31); nz % 8 == 0
     double *sig_hat, *sa64, *j;
@@ -61,7 +63,6 @@ struct Fine {
                                   // of which ghost faces (bits 6-11)
     int cbase;           // first global cluster index of this problem
     int ncl;             // clusters of this problem
-    void *b1;            // deflated V-cycle right-hand side (precision T)
 };
 
 // A run of cluster voxels: entries [start, start+count) of the problem's
@@ -72,6 +73,23 @@ struct CTask {
     int start;
     int count;
 };
+
+// Device workspace of one residual evaluation on a grid of at most
+// max_cells cells: D and the right-hand-side copy of r (max_cells doubles
+// each) and the problem descriptor.
+struct ResidualWork {
+    double *D;
+    double *b;
+    Fine *fine;
+    long long max_cells;
+};
+
+// Engine entry points for code outside fld_engine.cpp: the residual of a
+// device fluence of context c computed in workspace ws (nothing allocated),
+// and the HIP device a context runs on.
+fld_status residual_with_workspace(fld_context *c, const double *d_phi, double *d_r_out,
+                                   double *rel_out, const ResidualWork *ws);
+int context_device(const fld_context *c);
 
 // Per-problem device scalars.
 enum Scalar {
@@ -108,8 +126,7 @@ void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      double *partials, int mixed);
 void launch_rel(hipStream_t s, int nprob, double *scal, const int *active);
 void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
-                      const int *active, int b0_idx, double *pg, double *ps,
-                      const double *alpha, int mixed);
+                      const int *active, int b0_idx, double *pg, double *ps, int mixed);
 void launch_npcg_beta(hipStream_t s, int nprob, double *scal, const int *active, int first,
                       double restart_growth);
 void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
@@ -117,14 +134,14 @@ void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      double *prp, double *ppap, int mixed);
 void launch_npcg_theta(hipStream_t s, int nprob, double *scal, const int *active);
 // Cluster deflation: per-task partial sums of the cluster Galerkin diagonal
-// and of the right-hand side, the per-cluster coefficients alpha = s/d, the
-// deflated right-hand side b1 = b0 - A e1, and e0 += e1.
+// and of the right-hand side, the per-cluster coefficients alpha = s/d, and
+// the finest level's starting correction e0 = alpha[label].
 void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
                         const int *active, int b0_idx, double *pd, double *ps, int mixed);
 void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *cprob,
                         const double *pd, const double *ps, double *alpha, const int *active);
-void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
-                       const int *active, int b0_idx, const double *alpha, int mixed);
+void launch_defl_init(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const int *active, const double *alpha, int mixed);
 // Grid sequencing: the 2:1 coarsened medium (sigma_t, albedo, Q) from the
 // finest set-up fields, and the coarse fluence copied onto its 2x2x2 blocks.
 void launch_nested_coarsen(hipStream_t s, const double *sig_hat, const double *sa,
@@ -134,6 +151,8 @@ void launch_nested_prolong(hipStream_t s, const double *phi_c, int nx, int ny, i
                            double *phi);
 void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const double *scal, int colour, double omega, double *partials);
+// Write a problem descriptor to device memory (a kernel, not a copy).
+void launch_put_fine(hipStream_t s, const Fine &f, Fine *dst);
 
 // Multigrid level kernels, precision T = float (mixed) or double.  `grids`
 // is the device table of every level of every problem; a task names the grid

@@ -543,11 +543,10 @@ k_residual(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
 }
 
 // gamma = b0 . e and sigma = e . b0_prev (conjugate-gradient coefficients).
-// With deflation the cluster correction is first added: e0 += alpha[label].
 template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
-            double *pg, double *ps, const double *alpha)
+            double *pg, double *ps)
 {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
@@ -557,18 +556,17 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
             continue;
         const T *b = (const T *)f.b0[b0_idx];
         const T *bp = (const T *)f.b0[b0_idx ^ 1];
-        T *e = (T *)f.e0;
+        const T *e = (const T *)f.e0;
         double g = 0.0, sg = 0.0;
         const Dec dec(f.ny, f.nz);
         if ((f.nz & 3) == 0) {
             for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
                 const long long c0 = tk.start + 4 * (long long)q;
                 T eq[4], bq[4], bpq[4];
-                int q0 = 0;
                 if (sp) {
                     int i, j, k0;
                     dec(c0, i, j, k0);
-                    q0 = (i + j) & 1;
+                    const int q0 = (i + j) & 1;
                     ld4s(e, c0, q0, eq);
                     ld4s(b, c0, q0, bq);
                     ld4s(bp, c0, q0, bpq);
@@ -576,19 +574,6 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
                     ld4(e + c0, eq);
                     ld4(b + c0, bq);
                     ld4(bp + c0, bpq);
-                }
-                if (alpha) {
-                    int lq[4];
-                    ld4(f.label + c0, lq);
-                    if (lq[0] >= 0 || lq[1] >= 0 || lq[2] >= 0 || lq[3] >= 0) {
-                        for (int m = 0; m < 4; ++m)
-                            if (lq[m] >= 0)
-                                eq[m] = (T)(alpha[f.cbase + lq[m]] + (double)eq[m]);
-                        if (sp)
-                            st4s(e, c0, q0, eq);
-                        else
-                            st4(e + c0, eq);
-                    }
                 }
                 for (int m = 0; m < 4; ++m) {
                     const double ev = (double)eq[m];
@@ -605,15 +590,7 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
                 dec(c, i, j, k);
                 o = sidx(c, (i + j + k) & 1);
             }
-            double ev = (double)e[o];
-            if (alpha) {
-                const int l = f.label[c];
-                if (l >= 0) {
-                    ev = alpha[f.cbase + l] + ev;
-                    e[o] = (T)ev;
-                    ev = (double)e[o];
-                }
-            }
+            const double ev = (double)e[o];
             g += (double)b[o] * ev;
             sg += ev * (double)bp[o];
         }
@@ -833,13 +810,15 @@ k_defl_finish(const int *crange, const int *cprob, const double *pd, const doubl
         alpha[c] = s / d;
 }
 
-// Deflated right-hand side b1 = b0 - A e1 with e1 = alpha[label] (zero
-// outside clusters); A is the finest operator in the coefficients of the
-// V-cycle, (A x)_c = (x_c den - sum_s F_s x_s)/h^2.
+// Cluster deflation step as the finest level's starting correction:
+// e0 = alpha[label] (zero outside clusters).  The finest smoothing of the
+// V-cycle starts from it with the undeflated right-hand side; every step of
+// the cycle is affine in the correction and the right-hand side, so this is
+// e1 plus a cycle from zero on b0 - A e1, without forming A e1.
 template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
-k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active, int b0_idx,
-             const double *alpha)
+k_defl_init(const Fine *fines, const Task *tasks, int ntasks, const int *active,
+            const double *alpha)
 {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
@@ -847,135 +826,38 @@ k_defl_apply(const Fine *fines, const Task *tasks, int ntasks, const int *active
         const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob])
             continue;
-        const T *__restrict__ D = (const T *)f.D0;
-        const T *__restrict__ sa = (const T *)f.sa0;
-        const T *__restrict__ b = (const T *)f.b0[b0_idx];
-        T *__restrict__ b1 = (T *)f.b1;
+        T *__restrict__ e = (T *)f.e0;
         const int *__restrict__ lab = f.label;
         const double *__restrict__ al = alpha + f.cbase;
-        const long long sx = (long long)f.ny * f.nz, sy = f.nz;
-        const double gD0 = (double)(T)f.dghost;
         const Dec dec(f.ny, f.nz);
         if ((f.nz & 3) == 0) {
-            QuadSrc<T> Ds{D, 0, 0, sp};
-            auto A4 = [&](long long x, double v[4]) {
-                int l[4];
-                ld4(lab + x, l);
-                for (int m = 0; m < 4; ++m)
-                    v[m] = l[m] >= 0 ? al[l[m]] : 0.0;
-            };
-            auto A1 = [&](long long x) {
-                const int l = lab[x];
-                return l >= 0 ? al[l] : 0.0;
-            };
-            auto D4 = [&](long long x, double v[4]) {
-                T t[4];
-                Ds.quad(x, t);
-                for (int m = 0; m < 4; ++m)
-                    v[m] = (double)t[m];
-            };
-            auto D1 = [&](long long x) { return (double)Ds.one(x); };
             for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
                 const long long c0 = tk.start + 4 * (long long)q;
-                int i, j, k0;
-                dec(c0, i, j, k0);
-                const int q0 = (i + j) & 1;
-                Ds.c0 = c0;
-                Ds.q0 = q0;
-                Hood<double> Eh;
-                gather(Eh, A4, A1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, 0.0);
-                bool any = Eh.zl != 0.0 || Eh.zr != 0.0;
+                int l[4];
+                ld4(lab + c0, l);
+                T v[4];
                 for (int m = 0; m < 4; ++m)
-                    any = any || Eh.c[m] != 0.0 || Eh.xm[m] != 0.0 || Eh.xp[m] != 0.0 ||
-                          Eh.ym[m] != 0.0 || Eh.yp[m] != 0.0;
-                T bq[4];
-                if (sp)
-                    ld4s(b, c0, q0, bq);
-                else
-                    ld4(b + c0, bq);
-                if (!any) {
-                    if (sp)
-                        st4s(b1, c0, q0, bq);
-                    else
-                        st4(b1 + c0, bq);
-                    continue;
+                    v[m] = l[m] >= 0 ? (T)al[l[m]] : (T)0;
+                if (sp) {
+                    int i, j, k0;
+                    dec(c0, i, j, k0);
+                    st4s(e, c0, (i + j) & 1, v);
+                } else {
+                    st4(e + c0, v);
                 }
-                Hood<double> Dh;
-                gather(Dh, D4, D1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, gD0);
-                T saq[4], out[4];
-                if (sp)
-                    ld4s(sa, c0, q0, saq);
-                else
-                    ld4(sa + c0, saq);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    double Fc[6];
-                    quad_faces(Dh, i, j, k0, f.nx, f.ny, f.nz, f.mirror != 0, gD0, m, Fc);
-                    double nb = 0.0;
-                    double den = (double)saq[m] * f.h2;
-                    nb = nb + Fc[0] * Eh.xm[m]; den = den + Fc[0];
-                    nb = nb + Fc[1] * Eh.xp[m]; den = den + Fc[1];
-                    nb = nb + Fc[2] * Eh.ym[m]; den = den + Fc[2];
-                    nb = nb + Fc[3] * Eh.yp[m]; den = den + Fc[3];
-                    nb = nb + Fc[4] * Eh.zm(m); den = den + Fc[4];
-                    nb = nb + Fc[5] * Eh.zp(m); den = den + Fc[5];
-                    const double Ae = (Eh.c[m] * den - nb) / f.h2;
-                    out[m] = (T)((double)bq[m] - Ae);
-                }
-                if (sp)
-                    st4s(b1, c0, q0, out);
-                else
-                    st4(b1 + c0, out);
             }
             continue;
         }
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
-            int i, j, k;
-            dec(c, i, j, k);
-            auto ev = [&](bool in, long long x) {
-                if (!in)
-                    return 0.0;
-                const int l = lab[x];
-                return l >= 0 ? al[l] : 0.0;
-            };
-            const double e_c = ev(true, c);
-            const double exm = ev(i > 0, c - sx), exp_ = ev(i < f.nx - 1, c + sx);
-            const double eym = ev(j > 0, c - sy), eyp = ev(j < f.ny - 1, c + sy);
-            const double ezm = ev(k > 0, c - 1), ezp = ev(k < f.nz - 1, c + 1);
-            const int qc = (i + j + k) & 1;
-            const long long oc = sp ? sidx(c, qc) : c;
-            auto Dn = [&](long long x) { return (double)D[sp ? sidx(x, qc ^ 1) : x]; };
-            if (e_c == 0.0 && exm == 0.0 && exp_ == 0.0 && eym == 0.0 && eyp == 0.0 &&
-                ezm == 0.0 && ezp == 0.0) {
-                b1[oc] = b[oc];
-                continue;
+            long long o = c;
+            if (sp) {
+                int i, j, k;
+                dec(c, i, j, k);
+                o = sidx(c, (i + j + k) & 1);
             }
-            const double Dc = (double)D[oc];
-            const double gD = f.mirror ? Dc : gD0;
-            double nb = 0.0;
-            double den = (double)sa[oc] * f.h2;
-            double F;
-            F = 0.5 * (Dc + (i > 0 ? Dn(c - sx) : gD));
-            nb = nb + F * exm;
-            den = den + F;
-            F = 0.5 * (Dc + (i < f.nx - 1 ? Dn(c + sx) : gD));
-            nb = nb + F * exp_;
-            den = den + F;
-            F = 0.5 * (Dc + (j > 0 ? Dn(c - sy) : gD));
-            nb = nb + F * eym;
-            den = den + F;
-            F = 0.5 * (Dc + (j < f.ny - 1 ? Dn(c + sy) : gD));
-            nb = nb + F * eyp;
-            den = den + F;
-            F = 0.5 * (Dc + (k > 0 ? Dn(c - 1) : gD));
-            nb = nb + F * ezm;
-            den = den + F;
-            F = 0.5 * (Dc + (k < f.nz - 1 ? Dn(c + 1) : gD));
-            nb = nb + F * ezp;
-            den = den + F;
-            const double Ae = (e_c * den - nb) / f.h2;
-            b1[oc] = (T)((double)b[oc] - Ae);
+            const int l = lab[c];
+            e[o] = l >= 0 ? (T)al[l] : (T)0;
         }
     }
 }
@@ -1972,6 +1854,12 @@ k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, 
         e[r] = (T)y[r];
 }
 
+__global__ void k_put_fine(Fine f, Fine *dst)
+{
+    if (threadIdx.x == 0)
+        *dst = f;
+}
+
 inline int grid_for(int ntasks)
 {
     // Enough blocks to fill 256 CUs several times; blocks stride over tasks.
@@ -2049,11 +1937,10 @@ void launch_rel(hipStream_t s, int nprob, double *scal, const int *active)
 }
 
 void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
-                      const int *active, int b0_idx, double *pg, double *ps,
-                      const double *alpha, int mixed)
+                      const int *active, int b0_idx, double *pg, double *ps, int mixed)
 {
     hipLaunchKernelGGL(FLD_PICK(k_npcg_dots, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, b0_idx, pg, ps, alpha);
+                           tasks, ntasks, active, b0_idx, pg, ps);
 }
 
 void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
@@ -2073,11 +1960,11 @@ void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const i
                            ps, alpha, active);
 }
 
-void launch_defl_apply(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
-                       const int *active, int b0_idx, const double *alpha, int mixed)
+void launch_defl_init(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const int *active, const double *alpha, int mixed)
 {
-    hipLaunchKernelGGL(FLD_PICK(k_defl_apply, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
-                           tasks, ntasks, active, b0_idx, alpha);
+    hipLaunchKernelGGL(FLD_PICK(k_defl_init, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+                           tasks, ntasks, active, alpha);
 }
 
 void launch_nested_coarsen(hipStream_t s, const double *sig_hat, const double *sa,
@@ -2124,6 +2011,11 @@ void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int n
 {
     hipLaunchKernelGGL(k_alg1_pass, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines, tasks,
                        ntasks, scal, colour, omega, partials);
+}
+
+void launch_put_fine(hipStream_t s, const Fine &f, Fine *dst)
+{
+    hipLaunchKernelGGL(k_put_fine, dim3(1), dim3(64), 0, s, f, dst);
 }
 
 template <typename T>

@@ -186,9 +186,16 @@ def batch_config(nvol: int = 16, sizes=(64, 96, 128, 160, 192), albedos=(0.99, 0
         s = int(s)
         if size_scale != 1.0:
             s = max(16, int(round(s * size_scale / 8.0)) * 8)
-        h = 1.0 / s
-        st = cloud_extinction(value_noise(s, 5, 300 + v), 200.0, 0.40)
-        chans_a = [np.full_like(st, a) for a in albedos]
-        chans_q = [beer_lambert_source(st, a, h) for a in chans_a]
-        vols.append(dict(sigma_t=st, h=h, albedo=chans_a, Q=chans_q, n=s))
+        vols.append(batch_volume(s, v, albedos))
     return vols
+
+
+def batch_volume(s: int, v: int, albedos=(0.99, 0.95, 0.9)):
+    """Volume v of the batched workload at size s^3 (h = 1/s): 5-octave cloud
+    of seed 300 + v, sigma_t in [0, 200] with 40 % near-vacuum, one albedo and
+    single-scatter source per colour channel."""
+    h = 1.0 / s
+    st = cloud_extinction(value_noise(s, 5, 300 + v), 200.0, 0.40)
+    chans_a = [np.full_like(st, a) for a in albedos]
+    chans_q = [beer_lambert_source(st, a, h) for a in chans_a]
+    return dict(sigma_t=st, h=h, albedo=chans_a, Q=chans_q, n=s)

@@ -99,3 +99,17 @@ def test_batch_grid_sequencing_needs_even_axes():
     with pytest.raises(F.FldError) as ei:
         F.fld_batch_create(o, [(16, 16, 16), (10, 8, 5)], [1.0 / 16, 0.1], 1)
     assert ei.value.status == F.FLD_ERR_INVALID_ARGUMENT
+
+
+def test_one_library_copy_per_process():
+    # a context belongs to the copy of libfld.so that created it; asking the
+    # binding for a second copy (another path) in the same process is refused
+    F.lib()
+    saved = F.LIB_PATH
+    try:
+        F.LIB_PATH = saved + ".other"
+        with pytest.raises(RuntimeError, match="already loaded"):
+            F.lib()
+    finally:
+        F.LIB_PATH = saved
+    assert F.lib() is not None
