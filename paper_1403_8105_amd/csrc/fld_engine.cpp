@@ -141,15 +141,36 @@ struct fld_engine_impl {
         }
         return ev_pool[ev_used++];
     }
-    // Under capture the record becomes an event-record node of the graph
-    // (re-recorded on every replay); the runtime links it after the work
-    // captured so far.
+    // Under capture the record becomes an event-record node of the graph,
+    // re-recorded on every replay: the node is added after the nodes the
+    // stream's capture currently ends with and becomes the dependency of what
+    // is captured next.  The dependency list the runtime returns is used only
+    // by the very next call, before the capture's dependencies change.
     void record(hipEvent_t e)
     {
         if (!e)
             return;
-        note(hipEventRecordWithFlags(e, stream, capturing ? hipEventRecordExternal : 0),
-             "hipEventRecord");
+        if (!capturing) {
+            note(hipEventRecord(e, stream), "hipEventRecord");
+            return;
+        }
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        hipGraph_t g = nullptr;
+        const hipGraphNode_t *deps = nullptr;
+        size_t nd = 0;
+        hipError_t r = hipStreamGetCaptureInfo_v2(stream, &st, nullptr, &g, &deps, &nd);
+        if (r != hipSuccess || st != hipStreamCaptureStatusActive || !g) {
+            note(r != hipSuccess ? r : hipErrorIllegalState, "hipStreamGetCaptureInfo_v2");
+            return;
+        }
+        hipGraphNode_t node = nullptr;
+        r = hipGraphAddEventRecordNode(&node, g, deps, nd, e);
+        if (r != hipSuccess) {
+            note(r, "hipGraphAddEventRecordNode");
+            return;
+        }
+        note(hipStreamUpdateCaptureDependencies(stream, &node, 1, hipStreamSetCaptureDependencies),
+             "hipStreamUpdateCaptureDependencies");
     }
     // Timing events one captured outer iteration records: a pair around every
     // finest-level half-sweep, the limiter, the residual and the direction pass.

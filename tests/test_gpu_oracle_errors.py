@@ -39,9 +39,11 @@ _fixed = {}
 
 def oracle_floor(key, prob, tol, max_iters=3000, **kw):
     """The oracle's multigrid solve to `tol`, cached per key.  Any schedule
-    reaches the same fixed point; on the cloud media a solution at 1e-10
-    differs from one at the 1e-11 floor by about 3e-11 (relative L2, measured
-    on the 64^3 batch volumes), far below the 1e-5 gate."""
+    reaches the same fixed point.  The residual floor of these media lies
+    between 1e-13 and 3e-11 depending on the medium, so the references stop at
+    1e-10: such a solution differs from the one at the floor by 5e-12 to 3e-11
+    (relative L2, measured on the 64^3 batch volumes and the small ragged
+    grids), far below the 1e-5 gate."""
     if key not in _fixed:
         r = oracle.solve(prob, method="mg", tol=tol, max_iters=max_iters, **kw)
         assert r.status == "converged", (key, r.status, r.rel)
@@ -93,9 +95,9 @@ def test_batch_mixed_to_1e10_against_oracle_floor(parity_record):
     for v in vols:
         for c, a in enumerate(ALBEDOS):
             prob = oracle.setup(v["sigma_t"], v["albedo"][c], v["Q"][c], v["h"])
-            # the residual floor of these media is 1e-11 (64^3) to 2e-11 (96^3);
-            # at 96^3 the oracle stops at 1e-10 (about 400-600 iterations)
-            ref = oracle_floor(("c3", v["n"], a), prob, 1e-10 if v["n"] > 64 else 1.2e-11)
+            # the residual floor of these media lies between 1e-11 and 3e-11;
+            # the oracle stops at 1e-10 (about 300-600 iterations)
+            ref = oracle_floor(("c3", v["n"], a), prob, 1e-10)
             err = rel_l2(outs[q], ref.phi)
             _, rel_o, _ = oracle.nonlinear_residual(prob, outs[q])
             parity_record(test="batch_mixed_vs_oracle_floor", n=v["n"], albedo=a,
@@ -181,7 +183,7 @@ def test_mg_iterates_on_grids_off_the_quad_and_split_paths(shape, parity_record)
         s.close()
         np.testing.assert_allclose(rep["history"], ref.history, rtol=1e-9)
         assert rel_l2(phi, ref.phi) <= 1e-10, k
-    fixed = oracle_floor(("ragged", shape), prob, 1e-12)
+    fixed = oracle_floor(("ragged", shape), prob, 1e-10)
     s = F.Solver(shape, h, precision="mixed", tol=1e-10, max_iters=3000)
     s.set_medium(st, al, Q)
     phi, rep = s.solve()
