@@ -214,6 +214,23 @@ fld_status fld_residual(fld_context *c, const double *phi, double *r_out, double
 fld_status fld_residual_device(fld_context *c, const double *d_phi, double *d_r_out,
                                double *rel_out);
 
+/* Largest grid (cells) fld_residual_device_noalloc accepts: 128^3. */
+#define FLD_NOALLOC_MAX_CELLS 2097152LL
+
+/* fld_residual_device without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results bit-identical to
+ * fld_residual_device: d_phi (device, N values; NULL = the context's current
+ * fluence) is read in place, d_r_out (device, N values) may be NULL, *rel_out
+ * receives ||r||_2/||j||_2 (the call waits for the context's stream).  The
+ * temporaries live in a fixed scratch area of 2 * FLD_NOALLOC_MAX_CELLS
+ * doubles that the library holds on each GPU it runs on until the process
+ * ends; calls that overlap in time on one GPU share it and race.  Errors:
+ * INVALID_ARGUMENT for a NULL context or rel_out and for grids of more than
+ * FLD_NOALLOC_MAX_CELLS cells; STATE before a medium is set; DEVICE. */
+fld_status fld_residual_device_noalloc(fld_context *c, const double *d_phi, double *d_r_out,
+                                       double *rel_out);
+
 /* Free everything.  NULL is a no-op. */
 void fld_destroy(fld_context *c);
 

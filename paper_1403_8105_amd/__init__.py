@@ -62,7 +62,8 @@ EXPORTS = ["fld_default_options", "fld_create", "fld_set_medium", "fld_set_mediu
            "fld_solve", "fld_solve_device", "fld_solve_resume", "fld_residual",
            "fld_residual_device", "fld_destroy", "fld_status_string", "fld_last_error",
            "fld_batch_create", "fld_batch_set_volume", "fld_batch_solve", "fld_batch_destroy",
-           "fld_batch_last_error", "fld_device_arch", "fld_light_bake", "fld_render"]
+           "fld_batch_last_error", "fld_device_arch", "fld_light_bake", "fld_render",
+           "fld_residual_device_noalloc"]
 
 
 def lib():
@@ -96,6 +97,7 @@ def lib():
         L.fld_solve_resume.argtypes = [vp, vp, C.POINTER(fld_report)]
         L.fld_residual.argtypes = [vp, vp, vp, _dp]
         L.fld_residual_device.argtypes = [vp, vp, vp, _dp]
+        L.fld_residual_device_noalloc.argtypes = [vp, vp, vp, _dp]
         L.fld_destroy.argtypes = [vp]
         L.fld_destroy.restype = None
         L.fld_status_string.argtypes = [C.c_int]
@@ -233,6 +235,14 @@ def fld_residual(ctx, shape, phi=None, want_r=True):
 def fld_residual_device(ctx, d_phi: int = 0, d_r_out: int = 0):
     rel = C.c_double()
     _check(ctx, lib().fld_residual_device(ctx, d_phi or None, d_r_out or None, C.byref(rel)))
+    return rel.value
+
+
+def fld_residual_device_noalloc(ctx, d_phi: int = 0, d_r_out: int = 0):
+    """fld_residual_device without device allocations (fixed per-GPU scratch)."""
+    rel = C.c_double()
+    _check(ctx, lib().fld_residual_device_noalloc(ctx, d_phi or None, d_r_out or None,
+                                                  C.byref(rel)))
     return rel.value
 
 

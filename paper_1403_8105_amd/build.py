@@ -10,7 +10,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfld.so")
-SOURCES = ["csrc/fld_kernels.hip", "csrc/fld_engine.cpp", "csrc/fld_render.hip"]
+SOURCES = ["csrc/fld_kernels.hip", "csrc/fld_engine.cpp", "csrc/fld_render.hip",
+           "csrc/fld_noalloc.hip"]
 ARCH = os.environ.get("FLD_OFFLOAD_ARCH", "gfx950")
 
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
