@@ -90,6 +90,9 @@ struct fld_engine_impl {
     DevList coarse_cells[kMaxLevels];   // every cell of level l+1 (deep levels included)
     int *d_coarse_ids = nullptr, *d_deep_roots = nullptr;   // coarsest grids / deep roots
     int n_coarse = 0, n_deep = 0;
+    int *d_tail_roots = nullptr;   // problems whose tail runs in one workgroup launch
+    int n_tail = 0;
+    long long tail_lds = 0;
     int max_coarse_n = 1, max_coarse_bw = 1;
     // kernel instance choice: kmode 0 FP64, 1 FP32 natural, 2 FP32 colour-split,
     // 3 FP32 per problem; lsp the same for the level kernels (0 / 1 / 2)
@@ -532,7 +535,10 @@ struct fld_engine_impl {
         defl_enabled = opt.deflate_tau > 0.0;
         // deep part: from the first level (below the finest) with at most
         // opt.deep_cells cells; levels above it use the work-list kernels
-        std::vector<int> roots, coarsest;
+        // The tail (deep levels and coarsest solve) of a problem runs in one
+        // workgroup launch when its levels and LDS footprint fit that kernel,
+        // else as the per-phase deep kernels around the coarsest solve.
+        std::vector<int> roots, coarsest, tails;
         for (Prob &P : probs) {
             P.deep = P.nlev - 1;
             if (opt.deep_cells > 0)
@@ -541,9 +547,33 @@ struct fld_engine_impl {
                         P.deep = l;
                         break;
                     }
+            const int nd = P.nlev - 1 - P.deep;
+            const Level &Lc = P.lv[P.nlev - 1];
+            bool fused = nd <= 1 + tail_max_low() &&
+                         (nd == 0 || P.lv[P.deep].n <= tail_root_cells());
+            long long deep_cells = 0;
+            for (int l = P.deep; l < P.nlev - 1; ++l) {
+                deep_cells += P.lv[l].n;
+                if (l > P.deep && P.lv[l].n > tail_low_cells())
+                    fused = false;
+            }
+            const long long scratch = std::max<long long>(nd ? P.lv[P.deep].n : 0, Lc.n);
+            const long long need = tail_lds_need(Lc.n, (long long)Lc.ny * Lc.nz, deep_cells,
+                                                 scratch, (int)tsz);
+            if (fused && need <= tail_lds_limit()) {
+                tails.push_back(P.gid0 + P.deep);
+                tail_lds = std::max<long long>(tail_lds, need);
+                continue;
+            }
             if (P.deep < P.nlev - 1)
                 roots.push_back(P.gid0 + P.deep);
             coarsest.push_back(P.gid0 + P.nlev - 1);
+        }
+        n_tail = (int)tails.size();
+        if (n_tail) {
+            CK(dalloc(&d_tail_roots, sizeof(int) * n_tail));
+            HK(hipMemcpy(d_tail_roots, tails.data(), sizeof(int) * n_tail, hipMemcpyHostToDevice),
+               "hipMemcpy");
         }
         n_deep = (int)roots.size();
         if (n_deep) {
@@ -552,9 +582,11 @@ struct fld_engine_impl {
                "hipMemcpy");
         }
         n_coarse = (int)coarsest.size();
-        CK(dalloc(&d_coarse_ids, sizeof(int) * n_coarse));
-        HK(hipMemcpy(d_coarse_ids, coarsest.data(), sizeof(int) * n_coarse, hipMemcpyHostToDevice),
-           "hipMemcpy");
+        if (n_coarse) {
+            CK(dalloc(&d_coarse_ids, sizeof(int) * n_coarse));
+            HK(hipMemcpy(d_coarse_ids, coarsest.data(), sizeof(int) * n_coarse,
+                         hipMemcpyHostToDevice), "hipMemcpy");
+        }
         for (int l = 0; l < max_levels; ++l) {
             std::vector<Task> m, r, g, cc;
             // launch shape: task sizes from the cells all problems hold at this level
@@ -872,6 +904,8 @@ struct fld_engine_impl {
                 launch_restrict<T>(stream, G, rest[l].d, rest[l].n, d_active, lsp);
             }
         }
+        launch_tail<T>(stream, G, d_tail_roots, n_tail, d_active, d_fail, opt.nu1, opt.nu2,
+                       opt.omega_s, (int)tail_lds);
         launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.nu1, opt.omega_s, true);
         launch_coarse_solve<T>(stream, G, d_coarse_ids, n_coarse, d_active, d_fail, max_coarse_n,
                                max_coarse_bw);

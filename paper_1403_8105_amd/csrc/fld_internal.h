@@ -187,5 +187,21 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
 template <typename T>
 void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
                          const int *active, int *fail, int max_n, int max_bw);
+// Coarse tail in one launch per problem (one workgroup each): the deep levels
+// from a root (at most tail_root_cells() cells, then at most tail_max_low()
+// levels of at most tail_low_cells() cells) down to the coarsest solve and
+// back, bit-identical to launch_deep + launch_coarse_solve + launch_deep.  A
+// root equal to the coarsest level runs the coarsest solve alone.  lds_bytes:
+// the largest tail_lds_need() of the listed problems, at most
+// tail_lds_limit().
+template <typename T>
+void launch_tail(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
+                 int *fail, int nu1, int nu2, double omega, int lds_bytes);
+long long tail_lds_need(long long nc, long long bw, long long deep_cells, long long scratch_cells,
+                        int tsz);
+int tail_lds_limit();
+int tail_root_cells();
+int tail_low_cells();
+int tail_max_low();
 
 }  // namespace fld

@@ -1721,43 +1721,90 @@ k_deep_up(const Grid *grids, const int *roots, const int *active, int nu2, T ome
 // Coarsest level: e = M^{-1} (h^2 b) with M = h^2 A in natural order (half
 // bandwidth bw = ny*nz), factored by banded Cholesky in FP64 and solved in the
 // same launch.  Band entry (r, q), r - bw <= q <= r, sits at
-// band[r*(bw+1) + q - r + bw].  The factor is right-looking: after column c is
-// scaled, every entry of the trailing band subtracts L(r,c) L(q,c), so each
-// entry receives its subtractions in ascending column order, the order of the
-// textbook recurrence.  The forward substitution subtracts column by column
-// (again ascending) and the backward one row by row in ascending order, so
-// every value is rounded as in the textbook dense algorithm.  The band lives
-// in LDS when it fits (kCholLds bytes), else in global memory; a block of one
-// wavefront keeps the per-column barriers cheap.
-constexpr int kCholLds = 64 * 1024;
-
-// LDS: y and a row of products (2 max_n doubles), then the band if it fits.
-__host__ __device__ inline bool chol_in_lds(long long n, long long bw, long long max_n)
+// W[r*(bw+1) + q - r + bw].
+//
+// The factor is right-looking with the forward substitution folded in: at
+// column c every thread forms the multipliers it needs itself,
+// L(r,c) = W(r,c)/L(c,c), and subtracts L(r,c) L(q,c) from its trailing
+// entries and L(r,c) y_c from the right-hand side, so each entry receives its
+// subtractions in ascending column order, the order of the textbook
+// recurrence.  Column c is scaled in place one step later, when nothing reads
+// it any more, which leaves one barrier per column.  The backward
+// substitution runs row by row in one lane, each row's subtractions in
+// ascending order.  Every value is therefore rounded as in the textbook dense
+// algorithm.  W, diag (the factor's diagonal) and y (right-hand side in,
+// solution out) may live in LDS or global memory.  Returns false in every
+// thread when a pivot is not positive.
+__device__ bool chol_band(double *__restrict__ W, double *__restrict__ diag,
+                          double *__restrict__ y, int n, int bw)
 {
-    return n * (bw + 1) * 8 + 2 * max_n * 8 <= kCholLds;
+    const int Wd = bw + 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    bool bad = false;
+    for (int c = 0; c < n; ++c) {
+        const double d = W[(long long)c * Wd + bw];
+        bad = bad || !(d > 0.0);
+        const double lcc = sqrt(d);
+        if (c > 0) {
+            // column c-1 and y_{c-1} take their final (scaled) values
+            const double lp = diag[c - 1];
+            const int mp = min(bw, n - c);
+            for (int a = tid; a < mp; a += nt) {
+                double &w = W[(long long)(c + a) * Wd + (c - 1) - (c + a) + bw];
+                w = w / lp;
+            }
+            if (tid == nt - 1)
+                y[c - 1] = y[c - 1] / lp;
+        }
+        if (tid == 0)
+            diag[c] = lcc;
+        const int m = min(bw, n - 1 - c);       // rows below c in the band
+        const double yc = y[c] / lcc;
+        for (int x = tid; x < m * m; x += nt) {
+            const int a = x / m, bb = x - a * m;
+            if (bb > a)
+                continue;
+            const int r = c + 1 + a, q = c + 1 + bb;
+            const double lrc = W[(long long)r * Wd + c - r + bw] / lcc;
+            const double lqc = W[(long long)q * Wd + c - q + bw] / lcc;
+            double &t = W[(long long)r * Wd + q - r + bw];
+            t = t - lrc * lqc;
+        }
+        for (int a = tid; a < m; a += nt) {
+            const int r = c + 1 + a;
+            const double lrc = W[(long long)r * Wd + c - r + bw] / lcc;
+            y[r] = y[r] - lrc * yc;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        y[n - 1] = y[n - 1] / diag[n - 1];     // the forward substitution's last row
+        // L^T x = y, row by row, subtractions in ascending order
+        for (int r = n - 1; r >= 0; --r) {
+            const int m = min(bw, n - 1 - r);
+            double s = y[r];
+            for (int a = 1; a <= m; ++a)
+                s = s - W[(long long)(r + a) * Wd + r - (r + a) + bw] * y[r + a];
+            y[r] = s / diag[r];
+        }
+    }
+    __syncthreads();
+    return !bad;
 }
 
+// Rows of M = h^2 A for the coarsest grid g into the band W (one row per
+// thread; face loads independent of each other).
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, int max_n)
+__device__ void chol_assemble(const Grid &g, double *W)
 {
-    extern __shared__ double lds[];
-    const Grid &g = grids[ids[blockIdx.x]];
-    if (active && !active[g.prob])
-        return;
-    const int n = (int)g.n, bw = g.ny * g.nz, W = bw + 1;
-    double *y = lds;
-    double *L = chol_in_lds(n, bw, max_n) ? lds + 2 * max_n : g.band;
+    const int n = (int)g.n, bw = g.ny * g.nz, Wd = bw + 1;
     const double h2 = g.h2;
     const T *sa = (const T *)g.sa;
-    const T *b = (const T *)g.b;
-    T *e = (T *)g.e;
     const Dec dec(g.ny, g.nz);
-    // assemble: one row per thread, its face loads independent of each other
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         int i, j, k;
         dec(r, i, j, k);
-        double *row = L + (long long)r * W;       // row[q - r + bw]
+        double *row = W + (long long)r * Wd;       // row[q - r + bw]
         const double fx0 = (double)face_below<T>(g, 0, i, j, k);
         const double fx1 = (double)face_below<T>(g, 0, i + 1, j, k);
         const double fy0 = (double)face_below<T>(g, 1, i, j, k);
@@ -1780,78 +1827,309 @@ k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, 
             row[bw - g.nz] = -fy0;
         if (i > 0)
             row[0] = -fx0;
-        y[r] = (double)b[r] * h2;
     }
+}
+
+constexpr int kCholLds = 64 * 1024;
+
+// LDS: y and the diagonal (2 max_n doubles), then the band if it fits.
+__host__ __device__ inline bool chol_in_lds(long long n, long long bw, long long max_n)
+{
+    return n * (bw + 1) * 8 + 2 * max_n * 8 <= kCholLds;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, int max_n)
+{
+    extern __shared__ double lds[];
+    const Grid &g = grids[ids[blockIdx.x]];
+    if (active && !active[g.prob])
+        return;
+    const int n = (int)g.n, bw = g.ny * g.nz;
+    double *y = lds, *diag = lds + max_n;
+    double *W = chol_in_lds(n, bw, max_n) ? lds + 2 * max_n : g.band;
+    const T *b = (const T *)g.b;
+    chol_assemble<T>(g, W);
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+        y[r] = (double)b[r] * g.h2;
     __syncthreads();
-    // factor
-    bool bad = false;
-    for (int c = 0; c < n; ++c) {
-        if (threadIdx.x == 0) {
-            const double d = L[(long long)c * W + bw];
-            bad = bad || !(d > 0.0);
-            L[(long long)c * W + bw] = sqrt(d);
-        }
-        __syncthreads();
-        const double lcc = L[(long long)c * W + bw];
-        const int m = (c + bw < n - 1) ? bw : n - 1 - c;   // rows below c in the band
-        for (int a = threadIdx.x; a < m; a += blockDim.x) {
-            const int r = c + 1 + a;
-            L[(long long)r * W + c - r + bw] = L[(long long)r * W + c - r + bw] / lcc;
-        }
-        __syncthreads();
-        // trailing entries (r, q) = (c+1+a, c+1+bb), 0 <= bb <= a < m, enumerated
-        // row by row: x = a(a+1)/2 + bb
-        const int np = m * (m + 1) / 2;
-        for (int x = threadIdx.x; x < np; x += blockDim.x) {
-            int a = (int)((sqrtf(8.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
-            if ((a + 1) * (a + 2) / 2 <= x)
-                ++a;
-            if (a * (a + 1) / 2 > x)
-                --a;
-            const int bb = x - a * (a + 1) / 2;
-            const int r = c + 1 + a, q = c + 1 + bb;
-            const double lrc = L[(long long)r * W + c - r + bw];
-            const double lqc = L[(long long)q * W + c - q + bw];
-            double &t = L[(long long)r * W + q - r + bw];
-            t = t - lrc * lqc;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && bad)
+    const bool ok = chol_band(W, diag, y, n, bw);
+    if (threadIdx.x == 0 && !ok)
         fail[g.prob] = 1;
-    // L y = h^2 b, column by column
-    for (int c = 0; c < n; ++c) {
-        if (threadIdx.x == 0)
-            y[c] = y[c] / L[(long long)c * W + bw];
-        __syncthreads();
-        const double yc = y[c];
-        const int m = (c + bw < n - 1) ? bw : n - 1 - c;
-        for (int a = threadIdx.x; a < m; a += blockDim.x) {
-            const int r = c + 1 + a;
-            y[r] = y[r] - L[(long long)r * W + c - r + bw] * yc;
-        }
-        __syncthreads();
-    }
-    // L^T x = y, row by row: the products in parallel, their subtraction in
-    // ascending order by one lane
-    double *prod = y + n;
-    for (int r = n - 1; r >= 0; --r) {
-        const int m = (r + bw < n - 1) ? bw : n - 1 - r;
-        for (int a = threadIdx.x; a < m; a += blockDim.x) {
-            const int q = r + 1 + a;
-            prod[a] = L[(long long)q * W + r - q + bw] * y[q];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = y[r];
-            for (int a = 0; a < m; ++a)
-                s = s - prod[a];
-            y[r] = s / L[(long long)r * W + bw];
-        }
-        __syncthreads();
-    }
+    T *e = (T *)g.e;
     for (int r = threadIdx.x; r < n; r += blockDim.x)
         e[r] = (T)y[r];
+}
+
+// ---------------------------------------------------------------------------
+// Coarse tail in one launch: the deep levels of a problem (its root, the
+// first level of at most kTailRootCells cells, and up to two levels below it
+// of at most kTailLowCells cells each), pre-smoothing, restriction, the
+// coarsest Cholesky solve and the way back up, one workgroup per problem.
+// The corrections of the deep levels and the band live in LDS; each thread
+// keeps the face coefficients, b h^2 and the diagonal of the cells it owns
+// (cell c of a level belongs to thread c mod kTailBlock) in registers, so a
+// phase between two barriers touches LDS only.  Per cell the arithmetic is
+// exactly that of the work-list level kernels: the same neighbour order, the
+// same diagonal sum, the 8-child restriction in the same child order and the
+// parent prolongation, so results are bit-identical to the kernel-per-phase
+// path, which serves the problems whose tail does not fit.
+// ---------------------------------------------------------------------------
+constexpr int kTailBlock = 1024;
+constexpr int kTailRootCells = 4 * kTailBlock;
+constexpr int kTailLowCells = kTailBlock;
+constexpr int kTailMaxLow = 2;
+constexpr int kTailLds = 64 * 1024;
+
+template <typename T>
+struct CellCoef {
+    T F[6];     // faces x-, x+, y-, y+, z-, z+
+    T bh2;      // b h^2
+    T den;      // sa h^2 + sum of the faces
+};
+
+template <typename T>
+__device__ inline void tail_coef(const Grid &g, long long c, int i, int j, int k, CellCoef<T> &q,
+                                 bool with_b)
+{
+    const T h2 = (T)g.h2;
+    const long long fy = (long long)(g.nz + 1), fx = (long long)(g.ny + 1) * fy;
+    const long long nf = (long long)(g.nx + 1) * fx;
+    const long long fi = (long long)i * fx + (long long)j * fy + k;
+    const T *Fx = (const T *)g.f;
+    const T *Fy = Fx + nf;
+    const T *Fz = Fy + nf;
+    q.F[0] = Fx[fi];
+    q.F[1] = Fx[fi + fx];
+    q.F[2] = Fy[fi];
+    q.F[3] = Fy[fi + fy];
+    q.F[4] = Fz[fi];
+    q.F[5] = Fz[fi + 1];
+    T d_ = ((const T *)g.sa)[c] * h2;
+    for (int s = 0; s < 6; ++s)
+        d_ = d_ + q.F[s];
+    q.den = d_;
+    q.bh2 = with_b ? ((const T *)g.b)[c] * h2 : (T)0;
+}
+
+template <typename T>
+__device__ inline T tail_num(const CellCoef<T> &q, const T *e, long long c, int i, int j, int k,
+                             int nx, int ny, int nz)
+{
+    const long long sx = (long long)ny * nz, sy = nz;
+    T n_ = q.bh2;
+    n_ = n_ + q.F[0] * (i > 0 ? e[c - sx] : (T)0);
+    n_ = n_ + q.F[1] * (i < nx - 1 ? e[c + sx] : (T)0);
+    n_ = n_ + q.F[2] * (j > 0 ? e[c - sy] : (T)0);
+    n_ = n_ + q.F[3] * (j < ny - 1 ? e[c + sy] : (T)0);
+    n_ = n_ + q.F[4] * (k > 0 ? e[c - 1] : (T)0);
+    n_ = n_ + q.F[5] * (k < nz - 1 ? e[c + 1] : (T)0);
+    return n_;
+}
+
+// Phases over the cells a thread owns on one level (CPT cells per thread).
+template <typename T, int CPT>
+__device__ void tail_load(const Grid &g, CellCoef<T> (&q)[CPT], bool with_b)
+{
+    const Dec dec(g.ny, g.nz);
+#pragma unroll
+    for (int s = 0; s < CPT; ++s) {
+        const long long c = threadIdx.x + (long long)s * kTailBlock;
+        if (c < g.n) {
+            int i, j, k;
+            dec(c, i, j, k);
+            tail_coef<T>(g, c, i, j, k, q[s], with_b);
+        }
+    }
+}
+
+template <typename T, int CPT>
+__device__ void tail_smooth(const Grid &g, const CellCoef<T> (&q)[CPT], T *e, int colour, T omega)
+{
+    const Dec dec(g.ny, g.nz);
+#pragma unroll
+    for (int s = 0; s < CPT; ++s) {
+        const long long c = threadIdx.x + (long long)s * kTailBlock;
+        if (c < g.n) {
+            int i, j, k;
+            dec(c, i, j, k);
+            if (((i + j + k) & 1) != colour)
+                continue;
+            const T num = tail_num<T>(q[s], e, c, i, j, k, g.nx, g.ny, g.nz);
+            e[c] = omega * (num / q[s].den) + ((T)1 - omega) * e[c];
+        }
+    }
+}
+
+template <typename T, int CPT>
+__device__ void tail_residual(const Grid &g, const CellCoef<T> (&q)[CPT], const T *e, T *r)
+{
+    const Dec dec(g.ny, g.nz);
+    const T h2 = (T)g.h2;
+#pragma unroll
+    for (int s = 0; s < CPT; ++s) {
+        const long long c = threadIdx.x + (long long)s * kTailBlock;
+        if (c < g.n) {
+            int i, j, k;
+            dec(c, i, j, k);
+            const T num = tail_num<T>(q[s], e, c, i, j, k, g.nx, g.ny, g.nz);
+            r[c] = (num - e[c] * q[s].den) / h2;
+        }
+    }
+}
+
+template <typename T>
+__device__ void tail_zero(const Grid &g, T *e)
+{
+    for (long long c = threadIdx.x; c < g.n; c += kTailBlock)
+        e[c] = (T)0;
+}
+
+// e of level F += e of its parent on level C (both in LDS)
+template <typename T>
+__device__ void tail_prolong(const Grid &F, const Grid &C, T *ef, const T *ec)
+{
+    const T one = (T)1.0;
+    const Dec dec(F.ny, F.nz);
+    for (long long c = threadIdx.x; c < F.n; c += kTailBlock) {
+        int i, j, k;
+        dec(c, i, j, k);
+        ef[c] = ef[c] + one * ec[((long long)(i >> 1) * C.ny + (j >> 1)) * C.nz + (k >> 1)];
+    }
+}
+
+// 8-child mean of the residual r of level F for coarse cell (I, J, K).
+template <typename T>
+__device__ inline T tail_restrict(const Grid &F, const T *r, int I, int J, int K)
+{
+    T s = (T)0;
+    for (int di = 0; di < 2; ++di)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int dk = 0; dk < 2; ++dk)
+                s = s + r[((long long)(2 * I + di) * F.ny + (2 * J + dj)) * F.nz + (2 * K + dk)];
+    return (T)0.125 * s;
+}
+
+// LDS bytes the tail of a problem needs: band, diagonal and right-hand side of
+// the coarsest level (FP64), the deep levels' corrections and one residual /
+// coarsest-correction array (precision T).
+__host__ __device__ inline long long tail_lds_bytes(long long nc, long long bw, long long deep_cells,
+                                                    long long scratch_cells, int tsz)
+{
+    return (nc * (bw + 1) + 2 * nc) * 8 + (deep_cells + scratch_cells) * tsz;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kTailBlock)
+k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail, int nu1, int nu2,
+              T omega)
+{
+    extern __shared__ double lds[];
+    const int root = roots[blockIdx.x];
+    if (active && !active[grids[root].prob])
+        return;
+    int lv[kTailMaxLow + 2];
+    int nl = 0;
+    for (int gi = root;; gi = grids[gi].coarser) {
+        lv[nl++] = gi;
+        if (grids[gi].coarser < 0 || nl == kTailMaxLow + 2)
+            break;
+    }
+    const int nd = nl - 1;                     // smoothed (deep) levels
+    const Grid &Cg = grids[lv[nd]];
+    const int nc = (int)Cg.n, bw = Cg.ny * Cg.nz;
+    double *W = lds;
+    double *diag = W + (long long)nc * (bw + 1);
+    double *y = diag + nc;
+    T *e[kTailMaxLow + 1];
+    T *p = (T *)(y + nc);
+    for (int l = 0; l < nd; ++l) {
+        e[l] = p;
+        p += grids[lv[l]].n;
+    }
+    T *r = p;                                  // residual, then the coarsest correction
+    CellCoef<T> q0[4], q1[1], q2[1];
+    if (nd >= 1)
+        tail_load<T, 4>(grids[lv[0]], q0, true);
+    if (nd >= 2)
+        tail_load<T, 1>(grids[lv[1]], q1, false);
+    if (nd >= 3)
+        tail_load<T, 1>(grids[lv[2]], q2, false);
+    chol_assemble<T>(Cg, W);
+    if (nd == 0)
+        for (int c = threadIdx.x; c < nc; c += kTailBlock)
+            y[c] = (double)((const T *)Cg.b)[c] * Cg.h2;
+    // down: zero, nu1 pre-sweeps (red then black), restrict
+    for (int l = 0; l < nd; ++l) {
+        const Grid &g = grids[lv[l]];
+        tail_zero<T>(g, e[l]);
+        __syncthreads();
+        for (int s = 0; s < nu1; ++s)
+            for (int colour = 0; colour < 2; ++colour) {
+                if (l == 0)
+                    tail_smooth<T, 4>(g, q0, e[0], colour, omega);
+                else if (l == 1)
+                    tail_smooth<T, 1>(g, q1, e[1], colour, omega);
+                else
+                    tail_smooth<T, 1>(g, q2, e[2], colour, omega);
+                __syncthreads();
+            }
+        if (l == 0)
+            tail_residual<T, 4>(g, q0, e[0], r);
+        else if (l == 1)
+            tail_residual<T, 1>(g, q1, e[1], r);
+        else
+            tail_residual<T, 1>(g, q2, e[2], r);
+        __syncthreads();
+        const Grid &C = grids[lv[l + 1]];
+        const Dec dec(C.ny, C.nz);
+        for (long long cc = threadIdx.x; cc < C.n; cc += kTailBlock) {
+            int I, J, K;
+            dec(cc, I, J, K);
+            const T bv = tail_restrict<T>(g, r, I, J, K);
+            if (l + 1 == nd)
+                y[cc] = (double)bv * C.h2;
+            else if (l + 1 == 1)
+                q1[0].bh2 = bv * (T)C.h2;      // cc == threadIdx.x: one cell per thread
+            else
+                q2[0].bh2 = bv * (T)C.h2;
+        }
+        __syncthreads();
+    }
+    // coarsest (the band, y and the level data written above are complete)
+    __syncthreads();
+    const bool ok = chol_band(W, diag, y, nc, bw);
+    if (threadIdx.x == 0 && !ok)
+        fail[Cg.prob] = 1;
+    if (nd == 0) {
+        T *ec = (T *)Cg.e;
+        for (int c = threadIdx.x; c < nc; c += kTailBlock)
+            ec[c] = (T)y[c];
+        return;
+    }
+    for (int c = threadIdx.x; c < nc; c += kTailBlock)
+        r[c] = (T)y[c];
+    __syncthreads();
+    // up: prolongate, nu2 post-sweeps (black then red)
+    for (int l = nd - 1; l >= 0; --l) {
+        const Grid &g = grids[lv[l]];
+        tail_prolong<T>(g, grids[lv[l + 1]], e[l], l + 1 == nd ? r : e[l + 1]);
+        __syncthreads();
+        for (int s = 0; s < nu2; ++s)
+            for (int colour = 1; colour >= 0; --colour) {
+                if (l == 0)
+                    tail_smooth<T, 4>(g, q0, e[0], colour, omega);
+                else if (l == 1)
+                    tail_smooth<T, 1>(g, q1, e[1], colour, omega);
+                else
+                    tail_smooth<T, 1>(g, q2, e[2], colour, omega);
+                __syncthreads();
+            }
+    }
+    T *eg = (T *)grids[lv[0]].e;
+    for (long long c = threadIdx.x; c < grids[lv[0]].n; c += kTailBlock)
+        eg[c] = e[0][c];
 }
 
 __global__ void k_put_fine(Fine f, Fine *dst)
@@ -2069,12 +2347,31 @@ template <typename T>
 void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
                          const int *active, int *fail, int max_n, int max_bw)
 {
-    // one wavefront while the band fits in LDS, a full block otherwise
-    const int threads = chol_in_lds(max_n, max_bw, max_n) ? kWave : kBlock;
+    (void)max_bw;
     if (count > 0)
-        hipLaunchKernelGGL(k_coarse_solve<T>, dim3(count), dim3(threads), kCholLds, s, grids, ids,
+        hipLaunchKernelGGL(k_coarse_solve<T>, dim3(count), dim3(kBlock), kCholLds, s, grids, ids,
                            active, fail, max_n);
 }
+
+template <typename T>
+void launch_tail(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
+                 int *fail, int nu1, int nu2, double omega, int lds_bytes)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(k_coarse_tail<T>, dim3(count), dim3(kTailBlock), lds_bytes, s, grids,
+                           roots, active, fail, nu1, nu2, (T)omega);
+}
+
+long long tail_lds_need(long long nc, long long bw, long long deep_cells, long long scratch_cells,
+                        int tsz)
+{
+    return tail_lds_bytes(nc, bw, deep_cells, scratch_cells, tsz);
+}
+
+int tail_lds_limit() { return kTailLds; }
+int tail_root_cells() { return kTailRootCells; }
+int tail_low_cells() { return kTailLowCells; }
+int tail_max_low() { return kTailMaxLow; }
 
 template <typename T>
 void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
@@ -2097,7 +2394,9 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
     template void launch_coarse_solve<T>(hipStream_t, const Grid *, const int *, int,            \
                                          const int *, int *, int, int);                          \
     template void launch_deep<T>(hipStream_t, const Grid *, const int *, int, const int *, int,  \
-                                 double, bool);
+                                 double, bool);                                                  \
+    template void launch_tail<T>(hipStream_t, const Grid *, const int *, int, const int *, int *,  \
+                                 int, int, double, int);
 
 FLD_INSTANTIATE(float)
 FLD_INSTANTIATE(double)
