@@ -58,6 +58,8 @@ struct Vol {
 
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+constexpr int kRimTaskCells = 256;   // rim voxels per deflation rim task
+
 }  // namespace
 
 struct fld_engine_impl {
@@ -77,10 +79,10 @@ struct fld_engine_impl {
     // cluster deflation (built when the media are set)
     bool defl_enabled = false, use_defl = false;
     int ncl_total = 0;
-    CTask *d_ctasks = nullptr;
-    int n_ctasks = 0;
-    int *d_crange = nullptr, *d_cprob = nullptr;
-    double *d_alpha = nullptr, *d_cpd = nullptr, *d_cps = nullptr;
+    CTask *d_ctasks = nullptr, *d_rtasks = nullptr;   // cluster-cell and rim tasks
+    int n_ctasks = 0, n_rtasks = 0;
+    int *d_crange = nullptr, *d_rrange = nullptr, *d_cprob = nullptr;
+    double *d_alpha = nullptr, *d_csa = nullptr, *d_cpd = nullptr, *d_cps = nullptr;
     std::vector<void *> defl_allocs;
     int ngrids = 0;
     DevList fine_tasks;
@@ -702,7 +704,7 @@ struct fld_engine_impl {
         defl_allocs.clear();
         use_defl = false;
         ncl_total = 0;
-        n_ctasks = 0;
+        n_ctasks = n_rtasks = 0;
         if (!mg || !defl_enabled)
             return FLD_OK;
         auto dal = [&](void **q, size_t bytes) -> fld_status {
@@ -713,9 +715,9 @@ struct fld_engine_impl {
             return FLD_OK;
         };
         std::vector<int> vK(vols.size());
-        std::vector<int *> vlabel(vols.size()), vcells(vols.size());
+        std::vector<int *> vlabel(vols.size()), vpos(vols.size()), vrim(vols.size());
         std::vector<unsigned short *> vmask(vols.size());
-        std::vector<std::vector<int>> vstart(vols.size());
+        std::vector<std::vector<int>> vstart(vols.size()), vrstart(vols.size());
         for (size_t v = 0; v < vols.size(); ++v) {
             const Vol &V = vols[v];
             std::vector<double> sh(V.n);
@@ -723,6 +725,11 @@ struct fld_engine_impl {
             std::vector<int> label;
             const int K = label_clusters(V, sh, opt.deflate_tau, label);
             vK[v] = K;
+            // every channel of a volume has the same storage layout
+            bool split = false;
+            for (const Prob &P : probs)
+                if (P.vol == (int)v)
+                    split = P.fine.split != 0;
             // voxels of every cluster, cluster by cluster, index order inside
             std::vector<int> start(K + 1, 0), cells;
             for (long long c = 0; c < V.n; ++c)
@@ -735,51 +742,74 @@ struct fld_engine_impl {
             for (long long c = 0; c < V.n; ++c)
                 if (label[c] >= 0)
                     cells[fill[label[c]]++] = (int)c;
-            // faces leaving the cluster, in the order x-, x+, y-, y+, z-, z+
-            std::vector<unsigned short> mask(cells.size());
+            // their storage positions in the precision-T fields, and the rim
+            // voxels with the faces leaving the cluster (x-, x+, y-, y+, z-, z+)
+            std::vector<int> pos(cells.size()), rim, rstart(K + 1, 0);
+            std::vector<unsigned short> mask;
             const long long sx = (long long)V.ny * V.nz, sy = V.nz;
-            for (size_t q = 0; q < cells.size(); ++q) {
-                const long long c = cells[q];
-                const int k = (int)(c % V.nz), j = (int)((c / V.nz) % V.ny), i = (int)(c / sx);
-                const bool in[6] = {i > 0, i < V.nx - 1, j > 0, j < V.ny - 1, k > 0, k < V.nz - 1};
-                const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
-                unsigned short mk = 0;
-                for (int d = 0; d < 6; ++d) {
-                    if (!in[d])
-                        mk |= (unsigned short)((1u << d) | (1u << (d + 6)));
-                    else if (label[c + off[d]] != label[c])
-                        mk |= (unsigned short)(1u << d);
+            for (int q = 0; q < K; ++q) {
+                for (int e = start[q]; e < start[q + 1]; ++e) {
+                    const long long c = cells[e];
+                    const int k = (int)(c % V.nz), j = (int)((c / V.nz) % V.ny), i = (int)(c / sx);
+                    pos[e] = split ? (int)(((c >> 6) << 6) + (((i + j + k) & 1) << 5) + ((c >> 1) & 31))
+                                   : (int)c;
+                    const bool in[6] = {i > 0, i < V.nx - 1, j > 0, j < V.ny - 1, k > 0,
+                                        k < V.nz - 1};
+                    const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
+                    unsigned short mk = 0;
+                    for (int d = 0; d < 6; ++d) {
+                        if (!in[d])
+                            mk |= (unsigned short)((1u << d) | (1u << (d + 6)));
+                        else if (label[c + off[d]] != label[c])
+                            mk |= (unsigned short)(1u << d);
+                    }
+                    if (mk) {
+                        rim.push_back((int)c);
+                        mask.push_back(mk);
+                    }
                 }
-                mask[q] = mk;
+                rstart[q + 1] = (int)rim.size();
             }
             CK(dal((void **)&vlabel[v], sizeof(int) * V.n));
-            CK(dal((void **)&vcells[v], sizeof(int) * cells.size()));
+            CK(dal((void **)&vpos[v], sizeof(int) * pos.size()));
+            CK(dal((void **)&vrim[v], sizeof(int) * rim.size()));
             CK(dal((void **)&vmask[v], sizeof(unsigned short) * mask.size()));
-            if (!mask.empty())
-                HK(hipMemcpy(vmask[v], mask.data(), sizeof(unsigned short) * mask.size(),
-                             hipMemcpyHostToDevice), "cluster masks");
             HK(hipMemcpy(vlabel[v], label.data(), sizeof(int) * V.n, hipMemcpyHostToDevice), "labels");
-            if (!cells.empty())
-                HK(hipMemcpy(vcells[v], cells.data(), sizeof(int) * cells.size(),
-                             hipMemcpyHostToDevice), "cluster cells");
+            if (!pos.empty())
+                HK(hipMemcpy(vpos[v], pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice),
+                   "cluster positions");
+            if (!rim.empty()) {
+                HK(hipMemcpy(vrim[v], rim.data(), sizeof(int) * rim.size(), hipMemcpyHostToDevice),
+                   "rim cells");
+                HK(hipMemcpy(vmask[v], mask.data(), sizeof(unsigned short) * mask.size(),
+                             hipMemcpyHostToDevice), "rim masks");
+            }
             vstart[v] = start;
+            vrstart[v] = rstart;
         }
-        std::vector<CTask> ct;
-        std::vector<int> crange(1, 0), cprob;
+        std::vector<CTask> ct, rt;
+        std::vector<int> crange(1, 0), rrange(1, 0), cprob;
         std::vector<Fine> hf(nprob);
         for (int p = 0; p < nprob; ++p) {
             Fine &f = probs[p].fine;
             const int v = probs[p].vol;
             f.label = vlabel[v];
-            f.ccells = vcells[v];
-            f.cmask = vmask[v];
+            f.cpos = vpos[v];
+            f.rcells = vrim[v];
+            f.rmask = vmask[v];
             f.cbase = ncl_total;
             f.ncl = vK[v];
             for (int q = 0; q < vK[v]; ++q) {
                 for (int s0 = vstart[v][q]; s0 < vstart[v][q + 1]; s0 += kTaskCells)
                     ct.push_back(CTask{p, ncl_total + q, s0,
                                        std::min(kTaskCells, vstart[v][q + 1] - s0)});
+                // rim voxels gather neighbour coefficients: short tasks keep
+                // enough of them in flight
+                for (int s0 = vrstart[v][q]; s0 < vrstart[v][q + 1]; s0 += kRimTaskCells)
+                    rt.push_back(CTask{p, ncl_total + q, s0,
+                                       std::min(kRimTaskCells, vrstart[v][q + 1] - s0)});
                 crange.push_back((int)ct.size());
+                rrange.push_back((int)rt.size());
                 cprob.push_back(p);
             }
             ncl_total += vK[v];
@@ -789,15 +819,28 @@ struct fld_engine_impl {
         if (ncl_total == 0)
             return FLD_OK;
         n_ctasks = (int)ct.size();
+        n_rtasks = (int)rt.size();
         CK(dal((void **)&d_ctasks, sizeof(CTask) * ct.size()));
+        CK(dal((void **)&d_rtasks, sizeof(CTask) * std::max<size_t>(rt.size(), 1)));
         CK(dal((void **)&d_crange, sizeof(int) * crange.size()));
+        CK(dal((void **)&d_rrange, sizeof(int) * rrange.size()));
         CK(dal((void **)&d_cprob, sizeof(int) * cprob.size()));
         CK(dal((void **)&d_alpha, sizeof(double) * ncl_total));
-        CK(dal((void **)&d_cpd, sizeof(double) * ct.size()));
+        CK(dal((void **)&d_csa, sizeof(double) * ncl_total));
+        CK(dal((void **)&d_cpd, sizeof(double) * std::max<size_t>(rt.size(), 1)));
         CK(dal((void **)&d_cps, sizeof(double) * ct.size()));
         HK(hipMemcpy(d_ctasks, ct.data(), sizeof(CTask) * ct.size(), hipMemcpyHostToDevice), "ctasks");
+        if (!rt.empty())
+            HK(hipMemcpy(d_rtasks, rt.data(), sizeof(CTask) * rt.size(), hipMemcpyHostToDevice),
+               "rtasks");
         HK(hipMemcpy(d_crange, crange.data(), sizeof(int) * crange.size(), hipMemcpyHostToDevice), "crange");
+        HK(hipMemcpy(d_rrange, rrange.data(), sizeof(int) * rrange.size(), hipMemcpyHostToDevice), "rrange");
         HK(hipMemcpy(d_cprob, cprob.data(), sizeof(int) * cprob.size(), hipMemcpyHostToDevice), "cprob");
+        // the clusters' absorption sums, fixed for this medium
+        launch_defl_sum_sa(stream, d_fines, d_ctasks, n_ctasks, d_cps, mixed);
+        launch_defl_finish(stream, ncl_total, d_crange, d_rrange, d_cprob, d_cps, d_cpd, d_csa,
+                           d_alpha, nullptr, 1);
+        HK(hipGetLastError(), "cluster absorption");
         use_defl = true;
         return FLD_OK;
     }
@@ -979,10 +1022,10 @@ struct fld_engine_impl {
     {
         const int N = nprob;
         if (use_defl) {
-            launch_defl_reduce(stream, d_fines, d_ctasks, n_ctasks, d_active, k & 1, d_cpd, d_cps,
-                               kmode);
-            launch_defl_finish(stream, ncl_total, d_crange, d_cprob, d_cpd, d_cps, d_alpha,
-                               d_active);
+            launch_defl_sum_b(stream, d_fines, d_ctasks, n_ctasks, d_active, k & 1, d_cps, mixed);
+            launch_defl_rim(stream, d_fines, d_rtasks, n_rtasks, d_active, d_cpd, kmode);
+            launch_defl_finish(stream, ncl_total, d_crange, d_rrange, d_cprob, d_cps, d_cpd, d_csa,
+                               d_alpha, d_active, 0);
         }
         if (mixed) {
             coarsen<float>();

@@ -58,15 +58,17 @@ struct Fine {
     void *p[2];          // search-direction ping-pong (precision T)
     void *D0, *sa0;      // finest coefficients in precision T
     const int *label;    // cluster of each voxel (-1: none), per volume
-    const int *ccells;   // voxels of every cluster, cluster by cluster
-    const unsigned short *cmask;  // per ccells entry: faces leaving the cluster (bits 0-5),
+    const int *cpos;     // storage positions (precision-T fields) of the voxels of every
+                         // cluster, cluster by cluster, per volume
+    const int *rcells;   // rim voxels (a face leaves their cluster), cluster by cluster
+    const unsigned short *rmask;  // per rim voxel: faces leaving the cluster (bits 0-5),
                                   // of which ghost faces (bits 6-11)
     int cbase;           // first global cluster index of this problem
     int ncl;             // clusters of this problem
 };
 
 // A run of cluster voxels: entries [start, start+count) of the problem's
-// ccells list, all in global cluster `cl`.
+// cpos (cell tasks) or rcells (rim tasks) list, all in global cluster `cl`.
 struct CTask {
     int prob;
     int cl;
@@ -133,13 +135,21 @@ void launch_npcg_dir(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      const int *active, const double *scal, int b0_idx, int pin, int pout,
                      double *prp, double *ppap, int mixed);
 void launch_npcg_theta(hipStream_t s, int nprob, double *scal, const int *active);
-// Cluster deflation: per-task partial sums of the cluster Galerkin diagonal
-// and of the right-hand side, the per-cluster coefficients alpha = s/d, and
+// Cluster deflation.  launch_defl_sum_sa (once per medium): per cell task
+// the sum of sa over its cluster cells; launch_defl_sum_b: per cell task the
+// sum of b0; launch_defl_rim: per rim task the face terms F/h^2 of the faces
+// leaving the cluster; launch_defl_finish: per cluster the sums of its task
+// partials, into csa (sa_only) or alpha = s / (csa + rim); launch_defl_init:
 // the finest level's starting correction e0 = alpha[label].
-void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
-                        const int *active, int b0_idx, double *pd, double *ps, int mixed);
-void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *cprob,
-                        const double *pd, const double *ps, double *alpha, const int *active);
+void launch_defl_sum_sa(hipStream_t s, const Fine *fines, const CTask *ct, int nct, double *psa,
+                        int mixed);
+void launch_defl_sum_b(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
+                       const int *active, int b0_idx, double *ps, int mixed);
+void launch_defl_rim(hipStream_t s, const Fine *fines, const CTask *rt, int nrt,
+                     const int *active, double *pd, int mixed);
+void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *rrange,
+                        const int *cprob, const double *ps, const double *pd, double *csa,
+                        double *alpha, const int *active, int sa_only);
 void launch_defl_init(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const int *active, const double *alpha, int mixed);
 // Grid sequencing: the 2:1 coarsened medium (sigma_t, albedo, Q) from the

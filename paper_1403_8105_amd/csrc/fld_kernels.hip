@@ -726,88 +726,130 @@ k_npcg_dir(const Fine *fines, const Task *tasks, int ntasks, const int *active, 
     }
 }
 
-// Cluster deflation, reduction pass: for the voxels of each task (all in one
-// cluster) the contributions to the cluster Galerkin diagonal
-// d_c = sum sa + sum_{faces leaving c} F/h^2 and to s_c = sum b0.
-template <typename T, int SP>
+// Cluster deflation, reductions.  The cluster Galerkin diagonal is
+// d_c = sum_{p in c} sa_p + sum_{faces leaving c} F/h^2 and the right-hand
+// side sum s_c = sum_{p in c} b0_p.  The absorption sum depends on the medium
+// only and is formed once (k_defl_sum_sa); per outer iteration one pass sums
+// b0 over the cluster cells, read at their precomputed storage positions
+// (k_defl_sum_b), and one pass over the rim cells (cells with a face leaving
+// their cluster) sums the face terms from the current coefficients
+// (k_defl_rim).  A task covers cells (or rim cells) of one cluster; each
+// writes one partial.
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_defl_reduce(const Fine *fines, const CTask *ct, int nct, const int *active, int b0_idx,
-              double *pd, double *ps)
+k_defl_sum_sa(const Fine *fines, const CTask *ct, int nct, double *psa)
 {
     for (int t = blockIdx.x; t < nct; t += gridDim.x) {
         const CTask tk = ct[t];
         const Fine &f = fines[tk.prob];
+        const T *sa = (const T *)f.sa0;
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x)
+            acc += (double)sa[f.cpos[tk.start + q]];
+        acc = block_sum(acc);
+        if (threadIdx.x == 0)
+            psa[t] = acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_defl_sum_b(const Fine *fines, const CTask *ct, int nct, const int *active, int b0_idx, double *ps)
+{
+    for (int t = blockIdx.x; t < nct; t += gridDim.x) {
+        const CTask tk = ct[t];
+        const Fine &f = fines[tk.prob];
+        if (active && !active[f.prob]) {
+            if (threadIdx.x == 0)
+                ps[t] = 0.0;
+            continue;
+        }
+        const T *__restrict__ b = (const T *)f.b0[b0_idx];
+        const int *__restrict__ pos = f.cpos + tk.start;
+        double acc = 0.0;
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x)
+            acc += (double)b[pos[q]];
+        acc = block_sum(acc);
+        if (threadIdx.x == 0)
+            ps[t] = acc;
+    }
+}
+
+template <typename T, int SP>
+__global__ void __launch_bounds__(kBlock)
+k_defl_rim(const Fine *fines, const CTask *rt, int nrt, const int *active, double *pd)
+{
+    for (int t = blockIdx.x; t < nrt; t += gridDim.x) {
+        const CTask tk = rt[t];
+        const Fine &f = fines[tk.prob];
         const bool sp = layout_split<SP>(f.split);
         if (active && !active[f.prob]) {
-            if (threadIdx.x == 0) {
+            if (threadIdx.x == 0)
                 pd[t] = 0.0;
-                ps[t] = 0.0;
-            }
             continue;
         }
         const T *D = (const T *)f.D0;
-        const T *sa = (const T *)f.sa0;
-        const T *b = (const T *)f.b0[b0_idx];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
         const double gD0 = (double)(T)f.dghost;
         const Dec dec(f.ny, f.nz);
-        double ad = 0.0, as = 0.0;
+        double ad = 0.0;
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
-            const long long c = f.ccells[tk.start + q];
-            const int mask = f.cmask[tk.start + q];
+            const long long c = f.rcells[tk.start + q];
+            const int mask = f.rmask[tk.start + q];
             int qc = 0;
             if (sp) {
                 int i, j, k;
                 dec(c, i, j, k);
                 qc = (i + j + k) & 1;
             }
-            // own cell / a face neighbour (the other colour)
             auto at = [&](long long x, int qq) { return sp ? sidx(x, qq) : x; };
-            double v = (double)sa[at(c, qc)];
-            if (mask) {
-                // faces leaving the cluster: bit s set for neighbour s
-                // (x-, x+, y-, y+, z-, z+); bit s+6 set when it is a ghost
-                const double Dc = (double)D[at(c, qc)];
-                const double gD = f.mirror ? Dc : gD0;
-                const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
+            // faces leaving the cluster: bit s set for neighbour s (x-, x+,
+            // y-, y+, z-, z+); bit s+6 set when it is a ghost
+            const double Dc = (double)D[at(c, qc)];
+            const double gD = f.mirror ? Dc : gD0;
+            const long long off[6] = {-sx, sx, -sy, sy, -1, 1};
+            double v = 0.0;
 #pragma unroll
-                for (int d = 0; d < 6; ++d)
-                    if (mask & (1 << d)) {
-                        const bool ghost = (mask >> (d + 6)) & 1;
-                        const double F =
-                            0.5 * (Dc + (ghost ? gD : (double)D[at(c + off[d], qc ^ 1)]));
-                        v = v + F / f.h2;
-                    }
-            }
+            for (int d = 0; d < 6; ++d)
+                if (mask & (1 << d)) {
+                    const bool ghost = (mask >> (d + 6)) & 1;
+                    const double F = 0.5 * (Dc + (ghost ? gD : (double)D[at(c + off[d], qc ^ 1)]));
+                    v = v + F / f.h2;
+                }
             ad += v;
-            as += (double)b[at(c, qc)];
         }
         ad = block_sum(ad);
-        as = block_sum(as);
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0)
             pd[t] = ad;
-            ps[t] = as;
-        }
     }
 }
 
-// alpha_c = s_c / d_c, one block per cluster (sums of its task partials).
+// Per cluster: the sum of the partials of its cell tasks (range crange) and
+// of its rim tasks (range rrange), one block per cluster.  With sa_only the
+// cell partials are the absorption sums and go to csa; otherwise
+// alpha_c = s_c / (csa_c + rim_c).
 __global__ void __launch_bounds__(kBlock)
-k_defl_finish(const int *crange, const int *cprob, const double *pd, const double *ps,
-              double *alpha, const int *active)
+k_defl_finish(const int *crange, const int *rrange, const int *cprob, const double *ps,
+              const double *pd, double *csa, double *alpha, const int *active, int sa_only)
 {
     const int c = blockIdx.x;
     if (active && !active[cprob[c]])
         return;
-    double d = 0.0, s = 0.0;
-    for (int q = crange[c] + threadIdx.x; q < crange[c + 1]; q += blockDim.x) {
-        d += pd[q];
-        s += ps[q];
+    double sum = 0.0, rim = 0.0;
+    for (int q = crange[c] + threadIdx.x; q < crange[c + 1]; q += blockDim.x)
+        sum += ps[q];
+    sum = block_sum(sum);
+    if (!sa_only) {
+        for (int q = rrange[c] + threadIdx.x; q < rrange[c + 1]; q += blockDim.x)
+            rim += pd[q];
+        rim = block_sum(rim);
     }
-    d = block_sum(d);
-    s = block_sum(s);
-    if (threadIdx.x == 0)
-        alpha[c] = s / d;
+    if (threadIdx.x == 0) {
+        if (sa_only)
+            csa[c] = sum;
+        else
+            alpha[c] = sum / (csa[c] + rim);
+    }
 }
 
 // Cluster deflation step as the finest level's starting correction:
@@ -2221,21 +2263,48 @@ void launch_npcg_dots(hipStream_t s, const Fine *fines, const Task *tasks, int n
                            tasks, ntasks, active, b0_idx, pg, ps);
 }
 
-void launch_defl_reduce(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
-                        const int *active, int b0_idx, double *pd, double *ps, int mixed)
+void launch_defl_sum_sa(hipStream_t s, const Fine *fines, const CTask *ct, int nct, double *psa,
+                        int mixed)
 {
     if (nct <= 0)
         return;
-    hipLaunchKernelGGL(FLD_PICK(k_defl_reduce, mixed), dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
-                           ct, nct, active, b0_idx, pd, ps);
+    if (mixed)
+        hipLaunchKernelGGL(k_defl_sum_sa<float>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines, ct,
+                           nct, psa);
+    else
+        hipLaunchKernelGGL(k_defl_sum_sa<double>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
+                           ct, nct, psa);
 }
 
-void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *cprob,
-                        const double *pd, const double *ps, double *alpha, const int *active)
+void launch_defl_sum_b(hipStream_t s, const Fine *fines, const CTask *ct, int nct,
+                       const int *active, int b0_idx, double *ps, int mixed)
+{
+    if (nct <= 0)
+        return;
+    if (mixed)
+        hipLaunchKernelGGL(k_defl_sum_b<float>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines, ct,
+                           nct, active, b0_idx, ps);
+    else
+        hipLaunchKernelGGL(k_defl_sum_b<double>, dim3(grid_for(nct)), dim3(kBlock), 0, s, fines,
+                           ct, nct, active, b0_idx, ps);
+}
+
+void launch_defl_rim(hipStream_t s, const Fine *fines, const CTask *rt, int nrt,
+                     const int *active, double *pd, int mixed)
+{
+    if (nrt <= 0)
+        return;
+    hipLaunchKernelGGL(FLD_PICK(k_defl_rim, mixed), dim3(grid_for(nrt)), dim3(kBlock), 0, s, fines,
+                       rt, nrt, active, pd);
+}
+
+void launch_defl_finish(hipStream_t s, int ncl_total, const int *crange, const int *rrange,
+                        const int *cprob, const double *ps, const double *pd, double *csa,
+                        double *alpha, const int *active, int sa_only)
 {
     if (ncl_total > 0)
-        hipLaunchKernelGGL(k_defl_finish, dim3(ncl_total), dim3(kBlock), 0, s, crange, cprob, pd,
-                           ps, alpha, active);
+        hipLaunchKernelGGL(k_defl_finish, dim3(ncl_total), dim3(kBlock), 0, s, crange, rrange,
+                           cprob, ps, pd, csa, alpha, active, sa_only);
 }
 
 void launch_defl_init(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
