@@ -948,6 +948,43 @@ static int solve_alg1(const fldo_params *p, const fldo_solve_opts *o, const doub
     return status;
 }
 
+/* Anderson coefficients: gamma solves (G + lambda I) gamma = h with
+ * G_ij = dF_i . dF_j, h_i = dF_i . f over the *na history columns (column i
+ * of dF at dF + i*n), lambda = reg * trace(G) / na, by Cholesky.  When the
+ * factorisation fails the history is dropped (*na = 0). */
+static void anderson_coefficients(long n, int na, const double *dF, const double *f, double reg,
+                                  double *gam, int *na_out)
+{
+    double G[FLDO_MAX_AA * FLDO_MAX_AA], h[FLDO_MAX_AA];
+    *na_out = na;
+    if (na == 0)
+        return;
+    for (int i = 0; i < na; ++i) {
+        double hi = 0.0;
+        for (long c = 0; c < n; ++c)
+            hi += dF[(long)i * n + c] * f[c];
+        h[i] = hi;
+        for (int j = 0; j <= i; ++j) {
+            double g = 0.0;
+            for (long c = 0; c < n; ++c)
+                g += dF[(long)i * n + c] * dF[(long)j * n + c];
+            G[i * na + j] = g;
+            G[j * na + i] = g;
+        }
+    }
+    double tr = 0.0;
+    for (int i = 0; i < na; ++i)
+        tr += G[i * na + i];
+    const double lambda = reg * tr / (double)na;
+    for (int i = 0; i < na; ++i)
+        G[i * na + i] = G[i * na + i] + lambda;
+    if (fldo_cholesky_factor(na, G) != 0) {
+        *na_out = 0;
+        return;
+    }
+    fldo_cholesky_solve(na, G, h, gam);
+}
+
 /* Picard-multigrid with nonlinear preconditioned conjugate gradients.
  * Outer iteration k:
  *   D^k = limiter pass on phi^k (every voxel), r^k = j - A(D^k) phi^k (FP64),
@@ -961,7 +998,18 @@ static int solve_alg1(const fldo_params *p, const fldo_solve_opts *o, const doub
  *   theta_k = (r^k.p^k) / (p^k.A(D^k) p^k)  (energy-optimal step);
  *   phi^{k+1} = phi^k + theta_k p^k.
  * With a constant D (CDA) this is preconditioned CG on the linear system.
- * step_mode 0 replaces the direction and step by p = e, theta = option. */
+ * step_mode 0 replaces the direction and step by p = e, theta = option.
+ *
+ * aa_m > 0 replaces the conjugate-gradient step by Anderson acceleration of
+ * the preconditioned Picard map x -> x + e(x) (window m; Walker and Ni's
+ * formulation):
+ *   f_k = e^k; the history holds the last pairs dX_i = x_{i+1} - x_i,
+ *   dF_i = f_{i+1} - f_i, oldest first; after an iteration that raised the
+ *   residual norm by more than restart_growth (> 0) it is cleared;
+ *   G_ij = dF_i . dF_j, h_i = dF_i . f_k; gamma solves
+ *   (G + lambda I) gamma = h by Cholesky, lambda = aa_reg trace(G)/n_hist
+ *   (a failed factorisation clears the history);
+ *   x_{k+1} = x_k + f_k - sum_i gamma_i (dX_i + dF_i), the sum oldest first. */
 static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double *sig_hat,
                     const double *sig_a, const double *j_src, double *phi, double *hist,
                     int cap, fldo_result *res)
@@ -994,6 +1042,14 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
     memcpy(H.lv[0].sa, sig_a, sizeof(double) * n);
     int it = 0, len = 0, status = FLDO_NOT_CONVERGED, first = 1;
     double rel = NAN, rel_prev = NAN, gamma_prev = 0.0;
+    /* Anderson history: aa_m pairs (dX, dF), oldest first, plus f_{k-1} and
+     * the last step x_k - x_{k-1} */
+    const int am = o->aa_m > 0 ? o->aa_m : 0;
+    double *aX = am ? (double *)malloc(sizeof(double) * n * am) : NULL;
+    double *aF = am ? (double *)malloc(sizeof(double) * n * am) : NULL;
+    double *f_prev = am ? (double *)malloc(sizeof(double) * n) : NULL;
+    double *dx_last = am ? (double *)malloc(sizeof(double) * n) : NULL;
+    int na = 0;
     for (;;) {
         fldo_limiter_pass(p, phi, sig_hat, D);
         rel = fldo_residual(p, phi, D, sig_a, j_src, r) / p->jnorm;
@@ -1011,6 +1067,36 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
         }
         memcpy(H.lv[0].b, r, sizeof(double) * n);
         vcycle(H.lv, 0, nlev, o, d_ghost, p->mirror_d, H.chol, K > 0 ? e1 : NULL);
+        if (am) {
+            if (it > 0 && o->restart_growth > 0.0 && rel > o->restart_growth * rel_prev) {
+                na = 0;
+            } else if (it > 0) {
+                if (na == am) {
+                    memmove(aX, aX + n, sizeof(double) * n * (am - 1));
+                    memmove(aF, aF + n, sizeof(double) * n * (am - 1));
+                    --na;
+                }
+                for (long c = 0; c < n; ++c) {
+                    aX[(long)na * n + c] = dx_last[c];
+                    aF[(long)na * n + c] = e[c] - f_prev[c];
+                }
+                ++na;
+            }
+            rel_prev = rel;
+            memcpy(f_prev, e, sizeof(double) * n);
+            double gam[FLDO_MAX_AA];
+            anderson_coefficients(n, na, aF, e, o->aa_reg, gam, &na);
+            for (long c = 0; c < n; ++c) {
+                double step = e[c];
+                for (int i = 0; i < na; ++i)
+                    step = step - gam[i] * (aX[(long)i * n + c] + aF[(long)i * n + c]);
+                double x_new = phi[c] + step;
+                dx_last[c] = x_new - phi[c];
+                phi[c] = x_new;
+            }
+            ++it;
+            continue;
+        }
         double theta;
         if (o->step_mode == 1 || o->step_mode == 2) {
             double gamma = 0.0, e_rprev = 0.0;
@@ -1049,6 +1135,10 @@ static int solve_mg(const fldo_params *p, const fldo_solve_opts *o, const double
             phi[c] = phi[c] + theta * dir[c];
         ++it;
     }
+    free(aX);
+    free(aF);
+    free(f_prev);
+    free(dx_last);
     free(D);
     free(dir);
     free(q);

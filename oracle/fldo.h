@@ -7,6 +7,7 @@
 #define FLDO_H
 
 #define FLDO_MAX_LEVELS 16
+#define FLDO_MAX_AA 16
 
 enum {
     FLDO_LIMITER_CDA = 0,
@@ -58,6 +59,11 @@ typedef struct fldo_solve_opts {
     double restart_growth;    /* step_mode 1: restart when rel_k > restart_growth * rel_{k-1};
                                  <= 0 never restarts */
     double corr_scale;        /* factor on the prolongated coarse-grid correction */
+    int aa_m;                 /* > 0: Anderson acceleration with this window replaces the
+                                 conjugate-gradient step (the restart rule of step_mode 1
+                                 clears its history) */
+    double aa_reg;            /* Anderson: Tikhonov weight relative to the mean diagonal of
+                                 the Gram matrix */
 } fldo_solve_opts;
 
 typedef struct fldo_result {

@@ -366,3 +366,82 @@ def test_grid_sequencing_problem_and_fixed_point(oracle_mod):
     nest = oracle_mod.solve(prob, method="mg", tol=1e-10, max_iters=3000, nested_tol=1e-3)
     assert nest.status == "converged" and nest.nested_iterations > 0
     assert np.linalg.norm(nest.phi - plain.phi) <= 1e-8 * np.linalg.norm(plain.phi)
+
+
+def gmres_iterates(oracle_mod, D, sa, b, h, d_ghost, x0, k, **vk):
+    """Left-preconditioned GMRES for M A x = M b (M: one V-cycle, A: the
+    finest operator of frozen D), written here with numpy: the Arnoldi
+    process on the operator v -> M A v and the small least-squares problem;
+    returns the iterates x_0 .. x_k."""
+    shape = b.shape
+
+    def A(x):
+        return -oracle_mod.level_residual(D, sa, np.zeros(shape), x, h, d_ghost)
+
+    def M(r):
+        return oracle_mod.linear_vcycle(D, sa, r, h, d_ghost, **vk)
+
+    r0 = M(b - A(x0)).ravel()
+    beta = np.linalg.norm(r0)
+    V = [r0 / beta]
+    H = np.zeros((k + 1, k))
+    xs = [x0.copy()]
+    for j in range(k):
+        w = M(A(V[j].reshape(shape))).ravel()
+        for i in range(j + 1):
+            H[i, j] = V[i] @ w
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V.append(w / H[j + 1, j])
+        e1 = np.zeros(j + 2)
+        e1[0] = beta
+        y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+        xs.append(x0 + (np.stack(V[:j + 1], axis=1) @ y).reshape(shape))
+    return xs
+
+
+def test_anderson_on_a_linear_map_follows_gmres(oracle_mod):
+    # Walker and Ni (SIAM J. Numer. Anal. 2011), Thm 2.2: without truncation,
+    # Anderson acceleration of x -> g(x) = x + M(b - A x) yields
+    # x^AA_{k+1} = g(x^GMRES_k), GMRES applied to M A x = M b from the same
+    # start.  CDA makes D constant, so the outer iteration is that linear map
+    # (no deflation, no restarts, no regularisation).
+    st, al, Q, h = media.config("cloud128", n=16)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="cda")
+    phi0, _ = prob.init_state()
+    D = oracle_mod.limiter_pass(prob, phi0)
+    vk = dict(deflate_tau=0.0)
+    xs = gmres_iterates(oracle_mod, D, prob.sig_a, prob.j, h, EPS * h, phi0, 6)
+    for k in range(1, 7):
+        aa = oracle_mod.solve(prob, method="mg", tol=0.0, max_iters=k, aa_m=16, aa_reg=0.0,
+                              restart_growth=0.0, **vk)
+        x = xs[k - 1]
+        g = x + oracle_mod.linear_vcycle(D, prob.sig_a, prob.j - (-oracle_mod.level_residual(
+            D, prob.sig_a, np.zeros(x.shape), x, h, EPS * h)), h, EPS * h, **vk)
+        assert np.linalg.norm(aa.phi - g) <= 1e-8 * np.linalg.norm(g), k
+
+
+@pytest.mark.parametrize("case", ["point", "cloud"])
+def test_anderson_reaches_the_brute_force_fixed_point(oracle_mod, case):
+    if case == "point":
+        st, al, Q, h = media.point_source(8, sigma_t=10.0, albedo=0.9)
+    else:
+        st, al, Q, h = media.config("cloud128", n=8)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="lp")
+    ref = picard_direct(oracle_mod, prob, h)
+    aa = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000, aa_m=4)
+    assert aa.status == "converged"
+    assert np.linalg.norm(aa.phi - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_anderson_and_conjugate_gradient_share_the_fixed_point(oracle_mod):
+    # the 256^3 generator at 32^3 has vacuum clusters (deflation active) and
+    # residual growth in the first iterations (restarts active)
+    st, al, Q, h = media.config("cloud256", n=32)
+    prob = oracle_mod.setup(st, al, Q, h)
+    cg = oracle_mod.solve(prob, method="mg", tol=1e-10, max_iters=3000)
+    for m in (1, 4):
+        aa = oracle_mod.solve(prob, method="mg", tol=1e-10, max_iters=3000, aa_m=m)
+        assert aa.status == cg.status == "converged"
+        assert np.linalg.norm(aa.phi - cg.phi) <= 1e-8 * np.linalg.norm(cg.phi)
+    assert aa.iterations < cg.iterations
