@@ -314,7 +314,10 @@ def main():
     kms = np.sum([r["kernel_ms"] for r in reps], axis=0)
     kl = np.sum([r["kernel_launches"] for r in reps], axis=0)
     kb = np.sum([r["kernel_bytes"] for r in reps], axis=0)
-    kernels = {KERNEL_NAMES[q]: {"role": KERNEL_ROLES[q], "avg_us": 1e3 * kms[q] / kl[q],
+    names, roles = list(KERNEL_NAMES), list(KERNEL_ROLES)
+    if tuned[args.precision].get("aa_m"):
+        names[3], roles[3] = "k_aa_update", "Anderson update pass"
+    kernels = {names[q]: {"role": roles[q], "avg_us": 1e3 * kms[q] / kl[q],
                                  "launches": int(kl[q]),
                                  "alg_bytes_per_launch": kb[q] / kl[q],
                                  "GBps": (kb[q] / kl[q]) / (kms[q] / kl[q] * 1e-3) / 1e9}
@@ -352,7 +355,12 @@ def main():
         "config": {"workload": f"cloud {n}^3 FLD (Levermore-Pomraning), {desc}, "
                                f"Beer-Lambert source; {args.precision} Picard multigrid "
                                f"V({tuned[args.precision].get('nu1', 2)},"
-                               f"{tuned[args.precision].get('nu2', 2)}) to rel {args.tol:g}"
+                               f"{tuned[args.precision].get('nu2', 2)})"
+                               + (f" with Anderson acceleration (window "
+                                  f"{tuned[args.precision]['aa_m']})"
+                                  if tuned[args.precision].get("aa_m") else
+                                  " with nonlinear conjugate-gradient steps")
+                               + f" to rel {args.tol:g}"
                                + (f", started from the 2:1 coarser solve to "
                                   f"{tuned[args.precision]['nested_tol']:g}"
                                   if tuned[args.precision].get("nested_tol") else ""),

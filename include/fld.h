@@ -137,6 +137,15 @@ typedef struct fld_options {
                              (fld_batch_set_volume) in a second, coarse context (batch), 1/8
                              of the memory.  In a batch, a problem whose coarse solve
                              diverged starts from the paper's state.  0 disables (default)  */
+    int aa_m;             /* multigrid outer step: 0 the preconditioned nonlinear conjugate-
+                             gradient step (default); 1..16 Anderson acceleration of the
+                             preconditioned Picard map x -> x + e(x) with this window (the
+                             last aa_m pairs of differences of iterates and corrections,
+                             least squares by regularised normal equations); the
+                             restart_growth rule clears its history.  The coarse solve of
+                             grid sequencing keeps the default step                        */
+    double aa_reg;        /* Anderson: Tikhonov weight relative to the mean diagonal of the
+                             Gram matrix of correction differences (default 1e-10)          */
 } fld_options;
 
 typedef struct fld_report {
@@ -152,8 +161,9 @@ typedef struct fld_report {
     double voxel_updates; /* point updates applied (sweeps x cells, all levels)           */
     double bytes;         /* algorithmic HBM bytes of the timed kernels below             */
     /* With options.timing: per kernel class (0 finest-level smoother, 1 finest FP64
-     * residual, 2 limiter pass, 3 conjugate-direction pass) the summed HIP-event
-     * time, the number of launches and the algorithmic bytes those launches move. */
+     * residual, 2 limiter pass, 3 conjugate-direction pass or, with aa_m > 0, the
+     * Anderson update pass) the summed HIP-event time, the number of launches and
+     * the algorithmic bytes those launches move. */
     double kernel_ms[4];
     double kernel_launches[4];
     double kernel_bytes[4];

@@ -38,7 +38,8 @@ class fld_options(C.Structure):
                 ("graph", C.c_int), ("task_cells0", C.c_int), ("coarse_blocks", C.c_int),
                 ("colour_split", C.c_int), ("restart_growth", C.c_double),
                 ("corr_scale", C.c_double), ("anisotropy_g", C.c_double),
-                ("deep_cells", C.c_int), ("nested_tol", C.c_double)]
+                ("deep_cells", C.c_int), ("nested_tol", C.c_double), ("aa_m", C.c_int),
+                ("aa_reg", C.c_double)]
 
 
 class fld_report(C.Structure):

@@ -16,6 +16,11 @@ in device memory:
    tolerance wins.  ``quick`` keeps the default schedule and tunes only
    ``corr_scale`` and ``nested_tol``; ``refine`` starts from the cached
    entry and tries only ``nested_tol``.
+3. Outer step (``anderson``): Anderson acceleration windows (``aa_m``) in
+   place of the conjugate-gradient step for the winner, then a few schedules
+   and correction factors with the best window (the best smoothing schedule
+   changes with the outer step).  Starting from the cached entry it runs
+   alone.
 
 The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
 limiter), in ``tuned.json`` beside this file unless another path is given.
@@ -44,6 +49,9 @@ GROWTHS = [2.0, 10.0]
 SCALES = [1.0, 1.2, 1.4, 1.6, 1.8]
 NESTED = [1e-3, 1e-2]
 DEFAULT_SCHEDULE = (2, 2, 1.0, 2.0)
+AA_WINDOWS = [4, 8, 12, 16]
+AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.0)]
+AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 
 
 def cache_key(arch: str, shape, precision: str, limiter: str) -> str:
@@ -90,10 +98,12 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
          probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
-         quick: bool = False, refine: bool = False, schedules=None, scales=None) -> dict:
+         quick: bool = False, refine: bool = False, schedules=None, scales=None,
+         anderson: bool = False) -> dict:
     """Tune one grid/medium; stores and returns the cache entry.  ``schedules``
     ((nu1, nu2, omega_s, restart_growth) tuples) and ``scales`` replace the
-    default candidate lists (for grids whose full search is too long)."""
+    default candidate lists (for grids whose full search is too long).
+    ``anderson`` adds phase 3 (with ``refine``: phase 3 alone)."""
     import torch
 
     import paper_1403_8105_amd as F
@@ -130,18 +140,19 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     # full solves to tol
     results = []
 
-    def run(nu1, nu2, ws, gr, sc, nt=0.0):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0):
         o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
-                 nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc, nested_tol=nt)
+                 nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc, nested_tol=nt,
+                 aa_m=aa)
         ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "nested_tol": nt, "ms": ms,
+                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "ms": ms,
                         "iterations": rep["iterations"],
                         "nested_iterations": rep.get("nested_iterations", 0),
                         "rel": rep["rel"], "converged": ok})
         log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} corr_scale={sc} "
-            f"nested_tol={nt}: {rep['iterations']} its "
+            f"nested_tol={nt} aa_m={aa}: {rep['iterations']} its "
             f"(+{rep.get('nested_iterations', 0)} coarse), rel {rep['rel']:.2e}, {ms:.0f} ms"
             f"{'' if ok else ' (not converged)'}")
         return results[-1] if ok else None
@@ -152,7 +163,8 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     best = None
     if old:
         oo = old["options"]
-        best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"])
+        best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"],
+                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0))
     elif quick:
         best = run(*DEFAULT_SCHEDULE, 1.0)
     else:
@@ -165,15 +177,35 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         for sc in (scales or SCALES)[1:]:
             best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
                               sc), best)
-    if even:
+    if even and not (old and anderson):
         for nt in NESTED:
             best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
                               best["corr_scale"], nt), best)
+    if anderson:
+        # phase 3: Anderson windows for the winner, then schedules and
+        # correction factors with the best window
+        b0 = best
+        for m in AA_WINDOWS:
+            best = better(run(b0["nu1"], b0["nu2"], b0["omega_s"], b0["restart_growth"],
+                              b0["corr_scale"], b0.get("nested_tol", 0.0), m), best)
+        if best.get("aa_m"):
+            b1 = best
+            for nu1, nu2, ws in AA_SCHEDULES:
+                if (nu1, nu2, ws) != (b1["nu1"], b1["nu2"], b1["omega_s"]):
+                    best = better(run(nu1, nu2, ws, b1["restart_growth"], b1["corr_scale"],
+                                      b1.get("nested_tol", 0.0), b1["aa_m"]), best)
+            b2 = best
+            for sc in AA_SCALES:
+                if sc != b2["corr_scale"]:
+                    best = better(run(b2["nu1"], b2["nu2"], b2["omega_s"], b2["restart_growth"],
+                                      sc, b2.get("nested_tol", 0.0), b2["aa_m"]), best)
     opts = {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"], "nu2": best["nu2"],
             "omega_s": best["omega_s"], "restart_growth": best["restart_growth"],
             "corr_scale": best["corr_scale"]}
     if best.get("nested_tol"):
         opts["nested_tol"] = best["nested_tol"]
+    if best.get("aa_m"):
+        opts["aa_m"] = best["aa_m"]
     entry = {
         "options": opts,
         "tol": tol,
@@ -203,7 +235,7 @@ def batch_options(precision: str = "mixed", limiter: str = "lp", arch: str | Non
 
 def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
                max_iters: int = 5000, path: str | None = CACHE, log=print, schedules=None,
-               scales=None) -> dict:
+               scales=None, anderson: bool = False, refine: bool = False) -> dict:
     """Schedule search on the batched workload (``synth.media.batch_config``: 16
     cloud volumes x 3 colour channels): every candidate is one whole batched
     solve to the tolerance, default launch shapes; the shortest wins.  Grid
@@ -217,10 +249,10 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     allow = (F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED)
     results = []
 
-    def run(nu1, nu2, ws, gr, sc, nt=0.0):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0):
         o = F.fld_default_options(precision=precision, limiter=limiter, tol=tol,
                                   max_iters=max_iters, nu1=nu1, nu2=nu2, omega_s=ws,
-                                  restart_growth=gr, corr_scale=sc, nested_tol=nt)
+                                  restart_growth=gr, corr_scale=sc, nested_tol=nt, aa_m=aa)
         b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
         try:
             for q, v in enumerate(vols):
@@ -232,10 +264,10 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
             F.fld_batch_destroy(b)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "nested_tol": nt, "ms": ms,
+                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "ms": ms,
                         "iterations_max": int(its.max()), "converged": ok})
         log(f"autotune batch: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} "
-            f"corr_scale={sc} nested_tol={nt}: iterations {its.min()}..{its.max()} "
+            f"corr_scale={sc} nested_tol={nt} aa_m={aa}: iterations {its.min()}..{its.max()} "
             f"(+{rep.get('nested_iterations', 0)} coarse), {ms:.0f} ms"
             f"{'' if ok else ' (not converged)'}")
         return results[-1] if ok else None
@@ -244,27 +276,50 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
         return a if b is None or (a is not None and a["ms"] < b["ms"]) else b
 
     scs = scales or SCALES
-    cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
+    key = f"{device_arch()}|{BATCH_KEY}|{precision}|{limiter}"
+    old = load_cache(path or CACHE).get(key) if refine else None
+    if refine and not old:
+        raise RuntimeError(f"autotune batch: --refine needs a cached entry for {key}")
     best = None
-    for nu1, nu2, ws, gr in cands:
-        best = better(run(nu1, nu2, ws, gr, scs[0]), best)
+    if old:
+        oo = old["options"]
+        best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"],
+                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0))
+    else:
+        cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
+        for nu1, nu2, ws, gr in cands:
+            best = better(run(nu1, nu2, ws, gr, scs[0]), best)
     if best is None:
         raise RuntimeError("autotune batch: no schedule reached the tolerance")
-    for sc in scs[1:]:
-        best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"], sc),
-                      best)
-    if all(n % 2 == 0 for d in dims for n in d):
-        for nt in NESTED:
+    if not old:
+        for sc in scs[1:]:
             best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
-                              best["corr_scale"], nt), best)
+                              sc), best)
+        if all(n % 2 == 0 for d in dims for n in d):
+            for nt in NESTED:
+                best = better(run(best["nu1"], best["nu2"], best["omega_s"],
+                                  best["restart_growth"], best["corr_scale"], nt), best)
+    if anderson:
+        b0 = best
+        for m in AA_WINDOWS:
+            best = better(run(b0["nu1"], b0["nu2"], b0["omega_s"], b0["restart_growth"],
+                              b0["corr_scale"], b0["nested_tol"], m), best)
+        if best.get("aa_m"):
+            b1 = best
+            for nu1, nu2, ws in AA_SCHEDULES:
+                if (nu1, nu2, ws) != (b1["nu1"], b1["nu2"], b1["omega_s"]):
+                    best = better(run(nu1, nu2, ws, b1["restart_growth"], b1["corr_scale"],
+                                      b1["nested_tol"], b1["aa_m"]), best)
     keys = ("nu1", "nu2", "omega_s", "restart_growth", "corr_scale") + \
-        (("nested_tol",) if best["nested_tol"] else ())
+        (("nested_tol",) if best["nested_tol"] else ()) + (("aa_m",) if best.get("aa_m") else ())
     entry = {"options": {k: best[k] for k in keys},
              "tol": tol, "ms_to_tol": best["ms"], "iterations_max": best["iterations_max"],
              "schedules": results}
+    if old:
+        entry["schedules"] = old.get("schedules", []) + results
     if path:
         cache = load_cache(path)
-        cache[f"{device_arch()}|{BATCH_KEY}|{precision}|{limiter}"] = entry
+        cache[key] = entry
         with open(path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     return entry
@@ -285,6 +340,9 @@ def main(argv=None):
                     help="start from the cached entry; try only grid sequencing")
     ap.add_argument("--schedules", default=None,
                     help="candidate schedules 'nu1,nu2,omega_s,growth;...' (default: all)")
+    ap.add_argument("--anderson", action="store_true",
+                    help="also try Anderson windows for the outer step (with --refine: only "
+                         "that, from the cached entry)")
     ap.add_argument("--scales", default=None,
                     help="correction factors 'first,second,...'; the first goes with the "
                          "schedule search (default 1.0,1.2,1.4,1.6,1.8)")
@@ -299,7 +357,7 @@ def main(argv=None):
         entry = tune_batch(precision=args.precision, limiter=args.limiter, tol=args.tol,
                            max_iters=args.max_iters, path=args.out,
                            log=lambda m: print(m, flush=True), schedules=schedules,
-                           scales=scales)
+                           scales=scales, anderson=args.anderson, refine=args.refine)
         print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"]}),
               flush=True)
         return
@@ -307,7 +365,7 @@ def main(argv=None):
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
                  max_iters=args.max_iters, refine=args.refine, schedules=schedules,
-                 scales=scales)
+                 scales=scales, anderson=args.anderson)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"]}), flush=True)
 

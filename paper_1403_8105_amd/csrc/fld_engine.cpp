@@ -102,6 +102,9 @@ struct fld_engine_impl {
     int max_levels = 0;
     double *d_part[4] = {};
     double *d_scal = nullptr;
+    // Anderson acceleration: per-problem state and per-task partials
+    int *d_aai = nullptr;
+    double *d_aad = nullptr, *d_aapart = nullptr;
     int *d_active = nullptr, *d_fail = nullptr;
     std::vector<int> h_active;
     int k_state = 0;               // next outer iteration index (resume)
@@ -433,6 +436,12 @@ struct fld_engine_impl {
                     f.D0 = f.D64;
                     f.sa0 = f.sa64;
                 }
+                if (opt.aa_m > 0) {
+                    CK(dalloc(&f.aa_fprev, NT));
+                    HK(hipMemset(f.aa_fprev, 0, NT), "hipMemset");
+                    CK(dalloc(&f.aa_dX, NT * (opt.aa_m + 1)));
+                    CK(dalloc(&f.aa_dF, NT * (opt.aa_m + 1)));
+                }
             } else {
                 f.p[0] = f.p[1] = f.b0[1];
                 f.e0 = f.b0[1];
@@ -463,6 +472,12 @@ struct fld_engine_impl {
         HK(hipMemset(d_scal, 0, sizeof(double) * S_COUNT * nprob), "hipMemset");
         CK(dalloc(&d_active, sizeof(int) * nprob));
         CK(dalloc(&d_fail, sizeof(int) * nprob));
+        if (mg && opt.aa_m > 0) {
+            CK(dalloc(&d_aai, sizeof(int) * aa_state_ints() * nprob));
+            CK(dalloc(&d_aad, sizeof(double) * aa_state_doubles() * nprob));
+            HK(hipMemset(d_aad, 0, sizeof(double) * aa_state_doubles() * nprob), "hipMemset");
+            CK(dalloc(&d_aapart, sizeof(double) * 2 * (opt.aa_m + 1) * maxt));
+        }
         h_active.assign(nprob, 1);
         if (mg)
             CK(build_hierarchy());
@@ -999,6 +1014,9 @@ struct fld_engine_impl {
     {
         const int N = nprob;
         hipEvent_t ta = tic();
+        // with Anderson acceleration the update pass has written phi^k already
+        if (opt.aa_m > 0)
+            first = true;
         if (first)
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
                            k & 1, 0, 0, 0, kmode);
@@ -1033,6 +1051,20 @@ struct fld_engine_impl {
         } else {
             coarsen<double>();
             vcycle<double>(k & 1);
+        }
+        if (opt.aa_m > 0) {
+            const int m = opt.aa_m;
+            launch_aa_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_aai, d_aad, m,
+                           d_aapart, kmode);
+            launch_aa_sums(stream, N, d_fine_range, d_aapart, d_aai, d_aad, m, d_active);
+            launch_aa_solve(stream, N, d_scal, d_aai, d_aad, m, opt.aa_reg, opt.restart_growth,
+                            d_active);
+            hipEvent_t tu = tic();
+            launch_aa_update(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_aai, d_aad,
+                             k & 1, (k + 1) & 1, kmode);
+            // update: phi, e0 and the window's dX and dF read, phi and one dX written
+            toc(tu, 3, 16.0 + (2.0 + 2.0 * m) * tsz);
+            return;
         }
         launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_part[0],
                          d_part[1], kmode);
@@ -1104,6 +1136,8 @@ struct fld_engine_impl {
         }
         std::vector<double> sc;
         HK(hipMemsetAsync(d_fail, 0, sizeof(int) * N, stream), "memset");
+        if (opt.aa_m > 0 && start != 2)
+            launch_aa_reset(stream, N, d_aai);
         std::fill(h_active.begin(), h_active.end(), 1);
         CK(sync_active());
         const int first_k = k;
@@ -1304,6 +1338,8 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (!(o->nested_tol >= 0.0 && std::isfinite(o->nested_tol))) { err = "nested_tol must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->nested_tol > 0.0 && o->method != FLD_METHOD_MG) { err = "nested_tol needs the multigrid method"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->nested_tol > 0.0 && o->anisotropy_g != 0.0) { err = "nested_tol needs anisotropy_g = 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->aa_m < 0 || o->aa_m > aa_max_window()) { err = "aa_m must lie in [0,16]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (!(o->aa_reg >= 0.0 && std::isfinite(o->aa_reg))) { err = "aa_reg must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
 
@@ -1414,6 +1450,8 @@ fld_status fld_default_options(fld_options *o)
     o->anisotropy_g = 0.0;
     o->deep_cells = 4096;
     o->nested_tol = 0.0;
+    o->aa_m = 0;
+    o->aa_reg = 1e-10;
     return FLD_OK;
 }
 

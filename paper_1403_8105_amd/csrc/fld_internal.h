@@ -65,6 +65,9 @@ struct Fine {
                                   // of which ghost faces (bits 6-11)
     int cbase;           // first global cluster index of this problem
     int ncl;             // clusters of this problem
+    // Anderson acceleration (precision T, natural order): f of the previous
+    // iteration, and the history ring, slot s of dX / dF at s*n
+    void *aa_fprev, *aa_dX, *aa_dF;
 };
 
 // A run of cluster voxels: entries [start, start+count) of the problem's
@@ -161,6 +164,23 @@ void launch_nested_prolong(hipStream_t s, const double *phi_c, int nx, int ny, i
                            double *phi);
 void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const double *scal, int colour, double omega, double *partials);
+// Anderson acceleration of the outer iteration (window m <= aa_max_window()):
+// per-problem state aai (aa_state_ints() ints) and aad (aa_state_doubles()
+// doubles); reset at the start of a solve; per iteration dots (partials of
+// 2(m+1) values per task), sums, solve (one thread per problem) and update
+// phi[dst] = phi[src] + f - sum gamma (dX + dF).
+void launch_aa_reset(hipStream_t s, int nprob, int *aai);
+void launch_aa_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                    const int *active, int *aai, double *aad, int m, double *partials, int mixed);
+void launch_aa_sums(hipStream_t s, int nprob, const int *range, const double *partials, int *aai,
+                    double *aad, int m, const int *active);
+void launch_aa_solve(hipStream_t s, int nprob, double *scal, int *aai, double *aad, int m,
+                     double reg, double growth, const int *active);
+void launch_aa_update(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const int *active, int *aai, double *aad, int src, int dst, int mixed);
+int aa_max_window();
+int aa_state_ints();
+int aa_state_doubles();
 // Write a problem descriptor to device memory (a kernel, not a copy).
 void launch_put_fine(hipStream_t s, const Fine &f, Fine *dst);
 

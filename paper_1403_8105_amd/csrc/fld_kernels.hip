@@ -1082,6 +1082,295 @@ __global__ void k_npcg_theta(int nprob, double *scal, const int *active)
 }
 
 // ---------------------------------------------------------------------------
+// Anderson acceleration of the outer iteration (window m): the preconditioned
+// Picard map x -> x + f(x), f = the V-cycle's correction e0 (deflation
+// included).  The history lives in a ring of m+1 slots of precision-T vectors
+// in natural order (dX_s = x_{i+1} - x_i, dF_s = f_{i+1} - f_i); per problem a
+// small state records the committed slots oldest first, the slot whose dX is
+// pending (written by the last update, its dF formed by the next dots pass),
+// the Gram matrix G_st = dF_s . dF_t and the coefficients.  Per iteration:
+//   k_aa_dots    dF_p = f - f_prev into the pending slot p, f_prev = f, and
+//                per task the partials of dF_p . dF_s and dF_s . f for every
+//                slot s (dF_p for s = p);
+//   k_aa_sums    per problem those sums in task order;
+//   k_aa_solve   commit p (dropping the oldest when m are held) or, after an
+//                iteration that raised ||r|| by more than restart_growth,
+//                clear the history; gamma from (G + lambda I) gamma = h by
+//                Cholesky, lambda = reg trace(G)/count (a failed
+//                factorisation clears the history); choose the next pending
+//                slot;
+//   k_aa_update  x_{k+1} = x_k + f - sum_s gamma_s (dX_s + dF_s), oldest slot
+//                first, and dX of the pending slot = x_{k+1} - x_k.
+// ---------------------------------------------------------------------------
+constexpr int kAaMax = 16;                // largest window
+constexpr int kAaSlots = kAaMax + 1;
+
+// per-problem state: ints [order(kAaSlots), count, pending, pending_valid]
+// and doubles [G (kAaSlots^2), gamma, dots dF_p.dF_s, dots dF_s.f]
+constexpr int kAaInts = kAaSlots + 3;
+constexpr int kAaDbls = kAaSlots * kAaSlots + 3 * kAaSlots;
+
+struct AaView {
+    int *I;
+    double *G, *gam, *dd, *hf;
+    __device__ AaView(int *ints, double *dbls, int p)
+        : I(ints + p * kAaInts), G(dbls + (long long)p * kAaDbls),
+          gam(G + kAaSlots * kAaSlots), dd(gam + kAaSlots), hf(dd + kAaSlots) {}
+    __device__ int &count() { return I[kAaSlots]; }
+    __device__ int &pending() { return I[kAaSlots + 1]; }
+    __device__ int &pvalid() { return I[kAaSlots + 2]; }
+};
+
+// f = e0 of the cell / quad (colour-split or natural storage)
+template <typename T>
+__device__ inline double f_one(const Fine &f, bool sp, const Dec &dec, long long c)
+{
+    const T *e = (const T *)f.e0;
+    if (!sp)
+        return (double)e[c];
+    int i, j, k;
+    dec(c, i, j, k);
+    return (double)e[sidx(c, (i + j + k) & 1)];
+}
+
+template <typename T, int SP>
+__global__ void __launch_bounds__(kBlock)
+k_aa_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, int *aai,
+          double *aad, int m, double *partials)
+{
+    const int W = m + 1;
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
+        if (active && !active[f.prob])
+            continue;
+        AaView A(aai, aad, f.prob);
+        const int pnd = A.pending();
+        const long long n = f.n;
+        T *__restrict__ fprev = (T *)f.aa_fprev;
+        T *__restrict__ dF = (T *)f.aa_dF;           // slot s at dF + s*n
+        double g[kAaSlots], hs[kAaSlots];
+        for (int s = 0; s < kAaSlots; ++s)
+            g[s] = hs[s] = 0.0;
+        const Dec dec(f.ny, f.nz);
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            const double fv = f_one<T>(f, sp, dec, c);
+            const T dnew = (T)(fv - (double)fprev[c]);
+            fprev[c] = (T)fv;
+            dF[(long long)pnd * n + c] = dnew;
+            const double dn = (double)dnew;
+            // fully unrolled over the largest ring so the sums stay in registers;
+            // slots past the window are skipped uniformly
+#pragma unroll
+            for (int s = 0; s < kAaSlots; ++s) {
+                if (s < W) {
+                    const double v = s == pnd ? dn : (double)dF[(long long)s * n + c];
+                    g[s] += dn * v;
+                    hs[s] += v * fv;
+                }
+            }
+        }
+        // all 2W sums in one pass: wave shuffles, then one LDS row per wave
+        __shared__ double red[kBlock / kWave][2 * kAaSlots];
+        const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+        for (int s = 0; s < kAaSlots; ++s) {
+            if (s < W) {
+                double a = g[s], b = hs[s];
+                for (int o = kWave / 2; o > 0; o >>= 1) {
+                    a += __shfl_down(a, o, kWave);
+                    b += __shfl_down(b, o, kWave);
+                }
+                if (lane == 0) {
+                    red[wv][s] = a;
+                    red[wv][W + s] = b;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * W) {
+            double acc = 0.0;
+            for (int q = 0; q < kBlock / kWave; ++q)
+                acc += red[q][threadIdx.x];
+            partials[(long long)t * 2 * W + threadIdx.x] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// per problem: the sums of the 2(m+1) partials over its tasks, in task order
+__global__ void __launch_bounds__(kBlock)
+k_aa_sums(const int *range, const double *partials, int *aai, double *aad, int m,
+          const int *active)
+{
+    const int p = blockIdx.x;
+    if (active && !active[p])
+        return;
+    const int W = m + 1;
+    AaView A(aai, aad, p);
+    for (int w = 0; w < 2 * W; ++w) {
+        double acc = 0.0;
+        for (int q = range[p] + threadIdx.x; q < range[p + 1]; q += blockDim.x)
+            acc += partials[(long long)q * 2 * W + w];
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) {
+            if (w < W)
+                A.dd[w] = acc;
+            else
+                A.hf[w - W] = acc;
+        }
+    }
+}
+
+__global__ void k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m, double reg,
+                           double growth, const int *active)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob || (active && !active[p]))
+        return;
+    AaView A(aai, aad, p);
+    double *sc = scal + p * S_COUNT;
+    int *order = A.I;
+    int cnt = A.count();
+    const int pnd = A.pending();
+    if (A.pvalid()) {
+        if (growth > 0.0 && sc[S_REL] > growth * sc[S_REL_PREV]) {
+            cnt = 0;                                  // restart: clear the history
+        } else {
+            if (cnt == m) {                           // drop the oldest
+                for (int a = 0; a + 1 < cnt; ++a)
+                    order[a] = order[a + 1];
+                --cnt;
+            }
+            order[cnt++] = pnd;
+            for (int a = 0; a < cnt; ++a) {
+                const int s = order[a];
+                A.G[pnd * kAaSlots + s] = A.dd[s];
+                A.G[s * kAaSlots + pnd] = A.dd[s];
+            }
+        }
+    }
+    sc[S_REL_PREV] = sc[S_REL];
+    for (int s = 0; s < kAaSlots; ++s)
+        A.gam[s] = 0.0;
+    if (cnt > 0) {
+        // (G + lambda I) gamma = h over the committed slots, oldest first
+        double L[kAaMax * kAaMax], y[kAaMax];
+        double tr = 0.0;
+        for (int a = 0; a < cnt; ++a)
+            tr += A.G[order[a] * kAaSlots + order[a]];
+        const double lambda = reg * tr / (double)cnt;
+        for (int a = 0; a < cnt; ++a)
+            for (int b = 0; b < cnt; ++b)
+                L[a * kAaMax + b] = A.G[order[a] * kAaSlots + order[b]];
+        for (int a = 0; a < cnt; ++a)
+            L[a * kAaMax + a] = L[a * kAaMax + a] + lambda;
+        bool ok = true;
+        for (int c = 0; c < cnt && ok; ++c) {
+            double d = L[c * kAaMax + c];
+            for (int q = 0; q < c; ++q)
+                d = d - L[c * kAaMax + q] * L[c * kAaMax + q];
+            if (!(d > 0.0)) {
+                ok = false;
+                break;
+            }
+            const double lcc = sqrt(d);
+            L[c * kAaMax + c] = lcc;
+            for (int r = c + 1; r < cnt; ++r) {
+                double s = L[r * kAaMax + c];
+                for (int q = 0; q < c; ++q)
+                    s = s - L[r * kAaMax + q] * L[c * kAaMax + q];
+                L[r * kAaMax + c] = s / lcc;
+            }
+        }
+        if (ok) {
+            for (int r = 0; r < cnt; ++r) {
+                double s = A.hf[order[r]];
+                for (int q = 0; q < r; ++q)
+                    s = s - L[r * kAaMax + q] * y[q];
+                y[r] = s / L[r * kAaMax + r];
+            }
+            for (int r = cnt - 1; r >= 0; --r) {
+                double s = y[r];
+                for (int q = r + 1; q < cnt; ++q)
+                    s = s - L[q * kAaMax + r] * y[q];
+                y[r] = s / L[r * kAaMax + r];
+            }
+            for (int a = 0; a < cnt; ++a)
+                A.gam[order[a]] = y[a];
+        } else {
+            cnt = 0;
+        }
+    }
+    A.count() = cnt;
+    // the next pending slot: the lowest slot not in the history
+    int nxt = 0;
+    for (; nxt < m + 1; ++nxt) {
+        bool used = false;
+        for (int a = 0; a < cnt; ++a)
+            used = used || order[a] == nxt;
+        if (!used)
+            break;
+    }
+    A.pending() = nxt;
+    A.pvalid() = 1;
+}
+
+__global__ void k_aa_reset(int nprob, int *aai)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob)
+        return;
+    int *I = aai + p * kAaInts;
+    I[kAaSlots] = 0;        // count
+    I[kAaSlots + 1] = 0;    // pending slot
+    I[kAaSlots + 2] = 0;    // nothing pending
+}
+
+template <typename T, int SP>
+__global__ void __launch_bounds__(kBlock)
+k_aa_update(const Fine *fines, const Task *tasks, int ntasks, const int *active, int *aai,
+            double *aad, int src, int dst)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Fine &f = fines[tk.grid];
+        const bool sp = layout_split<SP>(f.split);
+        if (active && !active[f.prob])
+            continue;
+        AaView A(aai, aad, f.prob);
+        const int cnt = A.count(), pnd = A.pending();
+        int ord[kAaMax];
+        double gm[kAaMax];
+        for (int a = 0; a < cnt; ++a) {
+            ord[a] = A.I[a];
+            gm[a] = A.gam[ord[a]];
+        }
+        const long long n = f.n;
+        const double *__restrict__ x = f.phi[src];
+        double *__restrict__ xo = f.phi[dst];
+        const T *__restrict__ dX = (const T *)f.aa_dX;
+        const T *__restrict__ dF = (const T *)f.aa_dF;
+        T *__restrict__ dXp = (T *)f.aa_dX + (long long)pnd * n;
+        const Dec dec(f.ny, f.nz);
+        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+            const long long c = tk.start + q;
+            double step = f_one<T>(f, sp, dec, c);
+            for (int a = 0; a < cnt; ++a) {
+                const long long o = (long long)ord[a] * n + c;
+                step = step - gm[a] * ((double)dX[o] + (double)dF[o]);
+            }
+            const double xv = x[c];
+            const double xn = xv + step;
+            xo[c] = xn;
+            dXp[c] = (T)(xn - xv);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Multigrid levels, precision T
 // ---------------------------------------------------------------------------
 
@@ -2352,6 +2641,43 @@ void launch_npcg_theta(hipStream_t s, int nprob, double *scal, const int *active
 {
     hipLaunchKernelGGL(k_npcg_theta, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, active);
 }
+
+void launch_aa_reset(hipStream_t s, int nprob, int *aai)
+{
+    hipLaunchKernelGGL(k_aa_reset, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, aai);
+}
+
+void launch_aa_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                    const int *active, int *aai, double *aad, int m, double *partials, int mixed)
+{
+    hipLaunchKernelGGL(FLD_PICK(k_aa_dots, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s,
+                       fines, tasks, ntasks, active, aai, aad, m, partials);
+}
+
+void launch_aa_sums(hipStream_t s, int nprob, const int *range, const double *partials, int *aai,
+                    double *aad, int m, const int *active)
+{
+    hipLaunchKernelGGL(k_aa_sums, dim3(nprob), dim3(kBlock), 0, s, range, partials, aai, aad, m,
+                       active);
+}
+
+void launch_aa_solve(hipStream_t s, int nprob, double *scal, int *aai, double *aad, int m,
+                     double reg, double growth, const int *active)
+{
+    hipLaunchKernelGGL(k_aa_solve, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, aai, aad,
+                       m, reg, growth, active);
+}
+
+void launch_aa_update(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
+                      const int *active, int *aai, double *aad, int src, int dst, int mixed)
+{
+    hipLaunchKernelGGL(FLD_PICK(k_aa_update, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s,
+                       fines, tasks, ntasks, active, aai, aad, src, dst);
+}
+
+int aa_max_window() { return kAaMax; }
+int aa_state_ints() { return kAaInts; }
+int aa_state_doubles() { return kAaDbls; }
 
 void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                       const double *scal, int colour, double omega, double *partials)
