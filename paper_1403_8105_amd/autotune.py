@@ -49,7 +49,8 @@ GROWTHS = [2.0, 10.0]
 SCALES = [1.0, 1.2, 1.4, 1.6, 1.8]
 NESTED = [1e-3, 1e-2]
 DEFAULT_SCHEDULE = (2, 2, 1.0, 2.0)
-AA_WINDOWS = [4, 8, 12, 16]
+AA_WINDOWS = [6, 8, 10, 12, 16]
+AA_REGS = [1e-8, 1e-6]          # tried after the default 1e-10 for the best window
 AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.0)]
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 
@@ -140,14 +141,14 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     # full solves to tol
     results = []
 
-    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0, reg=1e-10):
         o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
                  nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc, nested_tol=nt,
-                 aa_m=aa)
+                 aa_m=aa, aa_reg=reg)
         ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "ms": ms,
+                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg, "ms": ms,
                         "iterations": rep["iterations"],
                         "nested_iterations": rep.get("nested_iterations", 0),
                         "rel": rep["rel"], "converged": ok})
@@ -164,7 +165,7 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     if old:
         oo = old["options"]
         best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"],
-                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0))
+                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0), oo.get("aa_reg", 1e-10))
     elif quick:
         best = run(*DEFAULT_SCHEDULE, 1.0)
     else:
@@ -199,6 +200,11 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                 if sc != b2["corr_scale"]:
                     best = better(run(b2["nu1"], b2["nu2"], b2["omega_s"], b2["restart_growth"],
                                       sc, b2.get("nested_tol", 0.0), b2["aa_m"]), best)
+            b3 = best
+            for reg in AA_REGS:
+                best = better(run(b3["nu1"], b3["nu2"], b3["omega_s"], b3["restart_growth"],
+                                  b3["corr_scale"], b3.get("nested_tol", 0.0), b3["aa_m"], reg),
+                              best)
     opts = {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"], "nu2": best["nu2"],
             "omega_s": best["omega_s"], "restart_growth": best["restart_growth"],
             "corr_scale": best["corr_scale"]}
@@ -206,6 +212,8 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         opts["nested_tol"] = best["nested_tol"]
     if best.get("aa_m"):
         opts["aa_m"] = best["aa_m"]
+        if best.get("aa_reg", 1e-10) != 1e-10:
+            opts["aa_reg"] = best["aa_reg"]
     entry = {
         "options": opts,
         "tol": tol,
@@ -249,10 +257,11 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     allow = (F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED)
     results = []
 
-    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0, reg=1e-10):
         o = F.fld_default_options(precision=precision, limiter=limiter, tol=tol,
                                   max_iters=max_iters, nu1=nu1, nu2=nu2, omega_s=ws,
-                                  restart_growth=gr, corr_scale=sc, nested_tol=nt, aa_m=aa)
+                                  restart_growth=gr, corr_scale=sc, nested_tol=nt, aa_m=aa,
+                                  aa_reg=reg)
         b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
         try:
             for q, v in enumerate(vols):
@@ -264,7 +273,7 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
             F.fld_batch_destroy(b)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "ms": ms,
+                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg, "ms": ms,
                         "iterations_max": int(its.max()), "converged": ok})
         log(f"autotune batch: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} "
             f"corr_scale={sc} nested_tol={nt} aa_m={aa}: iterations {its.min()}..{its.max()} "
@@ -284,7 +293,7 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     if old:
         oo = old["options"]
         best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"],
-                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0))
+                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0), oo.get("aa_reg", 1e-10))
     else:
         cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
         for nu1, nu2, ws, gr in cands:
@@ -310,8 +319,13 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
                 if (nu1, nu2, ws) != (b1["nu1"], b1["nu2"], b1["omega_s"]):
                     best = better(run(nu1, nu2, ws, b1["restart_growth"], b1["corr_scale"],
                                       b1["nested_tol"], b1["aa_m"]), best)
+            b3 = best
+            for reg in AA_REGS:
+                best = better(run(b3["nu1"], b3["nu2"], b3["omega_s"], b3["restart_growth"],
+                                  b3["corr_scale"], b3["nested_tol"], b3["aa_m"], reg), best)
     keys = ("nu1", "nu2", "omega_s", "restart_growth", "corr_scale") + \
-        (("nested_tol",) if best["nested_tol"] else ()) + (("aa_m",) if best.get("aa_m") else ())
+        (("nested_tol",) if best["nested_tol"] else ()) + (("aa_m",) if best.get("aa_m") else ()) + \
+        (("aa_reg",) if best.get("aa_m") and best.get("aa_reg", 1e-10) != 1e-10 else ())
     entry = {"options": {k: best[k] for k in keys},
              "tol": tol, "ms_to_tol": best["ms"], "iterations_max": best["iterations_max"],
              "schedules": results}

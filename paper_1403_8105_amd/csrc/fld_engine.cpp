@@ -106,7 +106,9 @@ struct fld_engine_impl {
     int *d_aai = nullptr;
     double *d_aad = nullptr, *d_aapart = nullptr;
     int *d_active = nullptr, *d_fail = nullptr;
-    std::vector<int> h_active;
+    std::vector<int> h_active, uploaded_active;
+    double *h_scal_pin = nullptr;   // pinned host copies of the scalars and the mask
+    int *h_active_pin = nullptr;
     int k_state = 0;               // next outer iteration index (resume)
     bool solved_once = false;
 
@@ -289,6 +291,10 @@ struct fld_engine_impl {
             hipFree(p);
         for (void *p : defl_allocs)
             hipFree(p);
+        if (h_scal_pin)
+            hipHostFree(h_scal_pin);
+        if (h_active_pin)
+            hipHostFree(h_active_pin);
         if (own_stream && stream)
             hipStreamDestroy(stream);
     }
@@ -439,8 +445,8 @@ struct fld_engine_impl {
                 if (opt.aa_m > 0) {
                     CK(dalloc(&f.aa_fprev, NT));
                     HK(hipMemset(f.aa_fprev, 0, NT), "hipMemset");
-                    CK(dalloc(&f.aa_dX, NT * (opt.aa_m + 1)));
                     CK(dalloc(&f.aa_dF, NT * (opt.aa_m + 1)));
+                    CK(dalloc(&f.aa_dG, NT * (opt.aa_m + 1)));
                 }
             } else {
                 f.p[0] = f.p[1] = f.b0[1];
@@ -472,6 +478,9 @@ struct fld_engine_impl {
         HK(hipMemset(d_scal, 0, sizeof(double) * S_COUNT * nprob), "hipMemset");
         CK(dalloc(&d_active, sizeof(int) * nprob));
         CK(dalloc(&d_fail, sizeof(int) * nprob));
+        HK(hipHostMalloc((void **)&h_scal_pin, sizeof(double) * S_COUNT * nprob, 0),
+           "hipHostMalloc");
+        HK(hipHostMalloc((void **)&h_active_pin, sizeof(int) * nprob, 0), "hipHostMalloc");
         if (mg && opt.aa_m > 0) {
             CK(dalloc(&d_aai, sizeof(int) * aa_state_ints() * nprob));
             CK(dalloc(&d_aad, sizeof(double) * aa_state_doubles() * nprob));
@@ -991,19 +1000,26 @@ struct fld_engine_impl {
 
     // ---- solves -----------------------------------------------------------
 
-    fld_status sync_active()
+    // The active mask goes to the device only when it changed (or when forced
+    // at the start of a solve); both directions of the per-iteration scalar
+    // traffic use pinned host buffers.
+    fld_status sync_active(bool force = false)
     {
-        HK(hipMemcpyAsync(d_active, h_active.data(), sizeof(int) * nprob, hipMemcpyHostToDevice,
+        if (!force && h_active == uploaded_active)
+            return FLD_OK;
+        std::copy(h_active.begin(), h_active.end(), h_active_pin);
+        HK(hipMemcpyAsync(d_active, h_active_pin, sizeof(int) * nprob, hipMemcpyHostToDevice,
                           stream), "active upload");
+        uploaded_active = h_active;
         return FLD_OK;
     }
 
     fld_status read_scalars(std::vector<double> &s)
     {
-        s.resize((size_t)S_COUNT * nprob);
-        HK(hipMemcpyAsync(s.data(), d_scal, sizeof(double) * S_COUNT * nprob,
+        HK(hipMemcpyAsync(h_scal_pin, d_scal, sizeof(double) * S_COUNT * nprob,
                           hipMemcpyDeviceToHost, stream), "scalars D2H");
         HK(hipStreamSynchronize(stream), "sync");
+        s.assign(h_scal_pin, h_scal_pin + (size_t)S_COUNT * nprob);
         return FLD_OK;
     }
 
@@ -1056,14 +1072,15 @@ struct fld_engine_impl {
             const int m = opt.aa_m;
             launch_aa_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_aai, d_aad, m,
                            d_aapart, kmode);
-            launch_aa_sums(stream, N, d_fine_range, d_aapart, d_aai, d_aad, m, d_active);
+            launch_aa_sums(stream, N, d_fine_range, d_aapart, fine_tasks.n, d_aai, d_aad, m,
+                           d_active);
             launch_aa_solve(stream, N, d_scal, d_aai, d_aad, m, opt.aa_reg, opt.restart_growth,
                             d_active);
             hipEvent_t tu = tic();
             launch_aa_update(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_aai, d_aad,
                              k & 1, (k + 1) & 1, kmode);
-            // update: phi, e0 and the window's dX and dF read, phi and one dX written
-            toc(tu, 3, 16.0 + (2.0 + 2.0 * m) * tsz);
+            // update: phi, e0 and the window's dG read, phi and one dG written
+            toc(tu, 3, 16.0 + (2.0 + 1.0 * m) * tsz);
             return;
         }
         launch_npcg_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, d_part[0],
@@ -1139,7 +1156,7 @@ struct fld_engine_impl {
         if (opt.aa_m > 0 && start != 2)
             launch_aa_reset(stream, N, d_aai);
         std::fill(h_active.begin(), h_active.end(), 1);
-        CK(sync_active());
+        CK(sync_active(true));
         const int first_k = k;
         *updates = 0.0;
         head(k, true);

@@ -66,8 +66,8 @@ struct Fine {
     int cbase;           // first global cluster index of this problem
     int ncl;             // clusters of this problem
     // Anderson acceleration (precision T, natural order): f of the previous
-    // iteration, and the history ring, slot s of dX / dF at s*n
-    void *aa_fprev, *aa_dX, *aa_dF;
+    // iteration, and the history ring, slot s of dF / dG = dX + dF at s*n
+    void *aa_fprev, *aa_dF, *aa_dG;
 };
 
 // A run of cluster voxels: entries [start, start+count) of the problem's
@@ -168,12 +168,12 @@ void launch_alg1_pass(hipStream_t s, const Fine *fines, const Task *tasks, int n
 // per-problem state aai (aa_state_ints() ints) and aad (aa_state_doubles()
 // doubles); reset at the start of a solve; per iteration dots (partials of
 // 2(m+1) values per task), sums, solve (one thread per problem) and update
-// phi[dst] = phi[src] + f - sum gamma (dX + dF).
+// phi[dst] = phi[src] + f - sum gamma dG, dG = dX + dF.
 void launch_aa_reset(hipStream_t s, int nprob, int *aai);
 void launch_aa_dots(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                     const int *active, int *aai, double *aad, int m, double *partials, int mixed);
-void launch_aa_sums(hipStream_t s, int nprob, const int *range, const double *partials, int *aai,
-                    double *aad, int m, const int *active);
+void launch_aa_sums(hipStream_t s, int nprob, const int *range, const double *partials,
+                    int ntasks, int *aai, double *aad, int m, const int *active);
 void launch_aa_solve(hipStream_t s, int nprob, double *scal, int *aai, double *aad, int m,
                      double reg, double growth, const int *active);
 void launch_aa_update(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,

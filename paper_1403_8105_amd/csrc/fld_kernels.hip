@@ -1083,15 +1083,18 @@ __global__ void k_npcg_theta(int nprob, double *scal, const int *active)
 
 // ---------------------------------------------------------------------------
 // Anderson acceleration of the outer iteration (window m): the preconditioned
-// Picard map x -> x + f(x), f = the V-cycle's correction e0 (deflation
+// Picard map x -> g(x) = x + f(x), f = the V-cycle's correction e0 (deflation
 // included).  The history lives in a ring of m+1 slots of precision-T vectors
-// in natural order (dX_s = x_{i+1} - x_i, dF_s = f_{i+1} - f_i); per problem a
-// small state records the committed slots oldest first, the slot whose dX is
-// pending (written by the last update, its dF formed by the next dots pass),
-// the Gram matrix G_st = dF_s . dF_t and the coefficients.  Per iteration:
-//   k_aa_dots    dF_p = f - f_prev into the pending slot p, f_prev = f, and
-//                per task the partials of dF_p . dF_s and dF_s . f for every
-//                slot s (dF_p for s = p);
+// in natural order: dF_s = f_{i+1} - f_i, and dG_s = dX_s + dF_s with
+// dX_s = x_{i+1} - x_i, so that the update
+//   x_{k+1} = x_k + f_k - sum_s gamma_s (dX_s + dF_s)
+// reads one history vector per slot.  Per problem a small state records the
+// committed slots oldest first, the pending slot (whose dG slot holds the dX
+// the last update wrote; the next dots pass adds dF to it), the Gram matrix
+// G_st = dF_s . dF_t and the coefficients.  Per iteration:
+//   k_aa_dots    dF_p = f - f_prev into the pending slot p, dG_p += dF_p,
+//                f_prev = f, and per task the partials of dF_p . dF_s and
+//                dF_s . f for every slot s (dF_p for s = p);
 //   k_aa_sums    per problem those sums in task order;
 //   k_aa_solve   commit p (dropping the oldest when m are held) or, after an
 //                iteration that raised ||r|| by more than restart_growth,
@@ -1099,8 +1102,9 @@ __global__ void k_npcg_theta(int nprob, double *scal, const int *active)
 //                Cholesky, lambda = reg trace(G)/count (a failed
 //                factorisation clears the history); choose the next pending
 //                slot;
-//   k_aa_update  x_{k+1} = x_k + f - sum_s gamma_s (dX_s + dF_s), oldest slot
-//                first, and dX of the pending slot = x_{k+1} - x_k.
+//   k_aa_update  x_{k+1} = x_k + f - sum_s gamma_s dG_s, oldest slot first,
+//                and dG of the pending slot = x_{k+1} - x_k.
+// A thread handles four consecutive cells (16-byte loads) when nz % 4 == 0.
 // ---------------------------------------------------------------------------
 constexpr int kAaMax = 16;                // largest window
 constexpr int kAaSlots = kAaMax + 1;
@@ -1121,7 +1125,7 @@ struct AaView {
     __device__ int &pvalid() { return I[kAaSlots + 2]; }
 };
 
-// f = e0 of the cell / quad (colour-split or natural storage)
+// f = e0 of a cell (colour-split or natural storage)
 template <typename T>
 __device__ inline double f_one(const Fine &f, bool sp, const Dec &dec, long long c)
 {
@@ -1133,12 +1137,27 @@ __device__ inline double f_one(const Fine &f, bool sp, const Dec &dec, long long
     return (double)e[sidx(c, (i + j + k) & 1)];
 }
 
+// f of the quad c0..c0+3 (c0 % 4 == 0)
+template <typename T>
+__device__ inline void f_quad(const Fine &f, bool sp, const Dec &dec, long long c0, T v[4])
+{
+    const T *e = (const T *)f.e0;
+    if (!sp) {
+        ld4(e + c0, v);
+        return;
+    }
+    int i, j, k0;
+    dec(c0, i, j, k0);
+    ld4s(e, c0, (i + j) & 1, v);
+}
+
 template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_aa_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, int *aai,
           double *aad, int m, double *partials)
 {
     const int W = m + 1;
+    __shared__ double red[kBlock / kWave][2 * kAaSlots];
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
         const Fine &f = fines[tk.grid];
@@ -1150,30 +1169,63 @@ k_aa_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, i
         const long long n = f.n;
         T *__restrict__ fprev = (T *)f.aa_fprev;
         T *__restrict__ dF = (T *)f.aa_dF;           // slot s at dF + s*n
+        T *__restrict__ dGp = (T *)f.aa_dG + (long long)pnd * n;
         double g[kAaSlots], hs[kAaSlots];
+#pragma unroll
         for (int s = 0; s < kAaSlots; ++s)
             g[s] = hs[s] = 0.0;
         const Dec dec(f.ny, f.nz);
-        for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
-            const long long c = tk.start + q;
-            const double fv = f_one<T>(f, sp, dec, c);
-            const T dnew = (T)(fv - (double)fprev[c]);
-            fprev[c] = (T)fv;
-            dF[(long long)pnd * n + c] = dnew;
-            const double dn = (double)dnew;
-            // fully unrolled over the largest ring so the sums stay in registers;
-            // slots past the window are skipped uniformly
+        if ((f.nz & 3) == 0) {
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                T fv[4], fp[4], dn[4], gp[4];
+                f_quad<T>(f, sp, dec, c0, fv);
+                ld4(fprev + c0, fp);
+                ld4(dGp + c0, gp);
+                for (int a = 0; a < 4; ++a) {
+                    dn[a] = (T)((double)fv[a] - (double)fp[a]);
+                    gp[a] = (T)((double)gp[a] + (double)dn[a]);
+                }
+                st4(fprev + c0, fv);
+                st4(dF + (long long)pnd * n + c0, dn);
+                st4(dGp + c0, gp);
 #pragma unroll
-            for (int s = 0; s < kAaSlots; ++s) {
-                if (s < W) {
-                    const double v = s == pnd ? dn : (double)dF[(long long)s * n + c];
-                    g[s] += dn * v;
-                    hs[s] += v * fv;
+                for (int s = 0; s < kAaSlots; ++s) {
+                    if (s < W) {
+                        T v[4];
+                        if (s == pnd)
+                            for (int a = 0; a < 4; ++a)
+                                v[a] = dn[a];
+                        else
+                            ld4(dF + (long long)s * n + c0, v);
+                        for (int a = 0; a < 4; ++a) {
+                            g[s] += (double)dn[a] * (double)v[a];
+                            hs[s] += (double)v[a] * (double)fv[a];
+                        }
+                    }
+                }
+            }
+        } else {
+            for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
+                const long long c = tk.start + q;
+                const double fv = f_one<T>(f, sp, dec, c);
+                const T dnew = (T)(fv - (double)fprev[c]);
+                fprev[c] = (T)fv;
+                dF[(long long)pnd * n + c] = dnew;
+                dGp[c] = (T)((double)dGp[c] + (double)dnew);
+                const double dn = (double)dnew;
+#pragma unroll
+                for (int s = 0; s < kAaSlots; ++s) {
+                    if (s < W) {
+                        const double v = s == pnd ? dn : (double)dF[(long long)s * n + c];
+                        g[s] += dn * v;
+                        hs[s] += v * fv;
+                    }
                 }
             }
         }
-        // all 2W sums in one pass: wave shuffles, then one LDS row per wave
-        __shared__ double red[kBlock / kWave][2 * kAaSlots];
+        // all 2W sums in one pass: wave shuffles, then one LDS row per wave;
+        // partials are stored value-major, partials[w * ntasks + t]
         const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 #pragma unroll
         for (int s = 0; s < kAaSlots; ++s) {
@@ -1194,45 +1246,61 @@ k_aa_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, i
             double acc = 0.0;
             for (int q = 0; q < kBlock / kWave; ++q)
                 acc += red[q][threadIdx.x];
-            partials[(long long)t * 2 * W + threadIdx.x] = acc;
+            partials[(long long)threadIdx.x * ntasks + t] = acc;
         }
         __syncthreads();
     }
 }
 
-// per problem: the sums of the 2(m+1) partials over its tasks, in task order
+// per problem: the sums of the 2(m+1) partials over its tasks, in a fixed
+// order; one block per (value, problem)
 __global__ void __launch_bounds__(kBlock)
-k_aa_sums(const int *range, const double *partials, int *aai, double *aad, int m,
+k_aa_sums(const int *range, const double *partials, int ntasks, int *aai, double *aad, int m,
           const int *active)
 {
-    const int p = blockIdx.x;
+    const int w = blockIdx.x, p = blockIdx.y;
     if (active && !active[p])
         return;
     const int W = m + 1;
     AaView A(aai, aad, p);
-    for (int w = 0; w < 2 * W; ++w) {
-        double acc = 0.0;
-        for (int q = range[p] + threadIdx.x; q < range[p + 1]; q += blockDim.x)
-            acc += partials[(long long)q * 2 * W + w];
-        acc = block_sum(acc);
-        if (threadIdx.x == 0) {
-            if (w < W)
-                A.dd[w] = acc;
-            else
-                A.hf[w - W] = acc;
-        }
+    const double *pw = partials + (long long)w * ntasks;
+    double acc = 0.0;
+    for (int q = range[p] + threadIdx.x; q < range[p + 1]; q += blockDim.x)
+        acc += pw[q];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) {
+        if (w < W)
+            A.dd[w] = acc;
+        else
+            A.hf[w - W] = acc;
     }
 }
 
-__global__ void k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m, double reg,
-                           double growth, const int *active)
+// one block per problem; the first thread solves in LDS
+__global__ void __launch_bounds__(kWave)
+k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m, double reg, double growth,
+           const int *active)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double L[kAaMax * kAaMax];
+    __shared__ double y[kAaMax];
+    __shared__ double Gs[kAaSlots * kAaSlots], dds[kAaSlots], hfs[kAaSlots];
+    __shared__ int order[kAaSlots];
+    const int p = blockIdx.x;
     if (p >= nprob || (active && !active[p]))
         return;
     AaView A(aai, aad, p);
+    // the state's doubles into LDS by the whole wavefront, then one lane
+    for (int q = threadIdx.x; q < kAaSlots * kAaSlots; q += blockDim.x)
+        Gs[q] = A.G[q];
+    for (int q = threadIdx.x; q < kAaSlots; q += blockDim.x) {
+        dds[q] = A.dd[q];
+        hfs[q] = A.hf[q];
+        order[q] = A.I[q];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
     double *sc = scal + p * S_COUNT;
-    int *order = A.I;
     int cnt = A.count();
     const int pnd = A.pending();
     if (A.pvalid()) {
@@ -1247,8 +1315,10 @@ __global__ void k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m
             order[cnt++] = pnd;
             for (int a = 0; a < cnt; ++a) {
                 const int s = order[a];
-                A.G[pnd * kAaSlots + s] = A.dd[s];
-                A.G[s * kAaSlots + pnd] = A.dd[s];
+                Gs[pnd * kAaSlots + s] = dds[s];
+                Gs[s * kAaSlots + pnd] = dds[s];
+                A.G[pnd * kAaSlots + s] = dds[s];
+                A.G[s * kAaSlots + pnd] = dds[s];
             }
         }
     }
@@ -1257,14 +1327,13 @@ __global__ void k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m
         A.gam[s] = 0.0;
     if (cnt > 0) {
         // (G + lambda I) gamma = h over the committed slots, oldest first
-        double L[kAaMax * kAaMax], y[kAaMax];
         double tr = 0.0;
         for (int a = 0; a < cnt; ++a)
-            tr += A.G[order[a] * kAaSlots + order[a]];
+            tr += Gs[order[a] * kAaSlots + order[a]];
         const double lambda = reg * tr / (double)cnt;
         for (int a = 0; a < cnt; ++a)
             for (int b = 0; b < cnt; ++b)
-                L[a * kAaMax + b] = A.G[order[a] * kAaSlots + order[b]];
+                L[a * kAaMax + b] = Gs[order[a] * kAaSlots + order[b]];
         for (int a = 0; a < cnt; ++a)
             L[a * kAaMax + a] = L[a * kAaMax + a] + lambda;
         bool ok = true;
@@ -1287,7 +1356,7 @@ __global__ void k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m
         }
         if (ok) {
             for (int r = 0; r < cnt; ++r) {
-                double s = A.hf[order[r]];
+                double s = hfs[order[r]];
                 for (int q = 0; q < r; ++q)
                     s = s - L[r * kAaMax + q] * y[q];
                 y[r] = s / L[r * kAaMax + r];
@@ -1305,6 +1374,8 @@ __global__ void k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m
         }
     }
     A.count() = cnt;
+    for (int a = 0; a < cnt; ++a)
+        A.I[a] = order[a];
     // the next pending slot: the lowest slot not in the history
     int nxt = 0;
     for (; nxt < m + 1; ++nxt) {
@@ -1351,21 +1422,42 @@ k_aa_update(const Fine *fines, const Task *tasks, int ntasks, const int *active,
         const long long n = f.n;
         const double *__restrict__ x = f.phi[src];
         double *__restrict__ xo = f.phi[dst];
-        const T *__restrict__ dX = (const T *)f.aa_dX;
-        const T *__restrict__ dF = (const T *)f.aa_dF;
-        T *__restrict__ dXp = (T *)f.aa_dX + (long long)pnd * n;
+        const T *__restrict__ dG = (const T *)f.aa_dG;
+        T *__restrict__ dGp = (T *)f.aa_dG + (long long)pnd * n;
         const Dec dec(f.ny, f.nz);
+        if ((f.nz & 3) == 0) {
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                T fv[4], dx[4];
+                double step[4], xv[4], xn[4];
+                f_quad<T>(f, sp, dec, c0, fv);
+                for (int a = 0; a < 4; ++a)
+                    step[a] = (double)fv[a];
+                for (int a = 0; a < cnt; ++a) {
+                    T v[4];
+                    ld4(dG + (long long)ord[a] * n + c0, v);
+                    for (int b = 0; b < 4; ++b)
+                        step[b] = step[b] - gm[a] * (double)v[b];
+                }
+                ld4(x + c0, xv);
+                for (int b = 0; b < 4; ++b) {
+                    xn[b] = xv[b] + step[b];
+                    dx[b] = (T)(xn[b] - xv[b]);
+                }
+                st4(xo + c0, xn);
+                st4(dGp + c0, dx);
+            }
+            continue;
+        }
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             double step = f_one<T>(f, sp, dec, c);
-            for (int a = 0; a < cnt; ++a) {
-                const long long o = (long long)ord[a] * n + c;
-                step = step - gm[a] * ((double)dX[o] + (double)dF[o]);
-            }
+            for (int a = 0; a < cnt; ++a)
+                step = step - gm[a] * (double)dG[(long long)ord[a] * n + c];
             const double xv = x[c];
             const double xn = xv + step;
             xo[c] = xn;
-            dXp[c] = (T)(xn - xv);
+            dGp[c] = (T)(xn - xv);
         }
     }
 }
@@ -2654,18 +2746,18 @@ void launch_aa_dots(hipStream_t s, const Fine *fines, const Task *tasks, int nta
                        fines, tasks, ntasks, active, aai, aad, m, partials);
 }
 
-void launch_aa_sums(hipStream_t s, int nprob, const int *range, const double *partials, int *aai,
-                    double *aad, int m, const int *active)
+void launch_aa_sums(hipStream_t s, int nprob, const int *range, const double *partials,
+                    int ntasks, int *aai, double *aad, int m, const int *active)
 {
-    hipLaunchKernelGGL(k_aa_sums, dim3(nprob), dim3(kBlock), 0, s, range, partials, aai, aad, m,
-                       active);
+    hipLaunchKernelGGL(k_aa_sums, dim3(2 * (m + 1), nprob), dim3(kBlock), 0, s, range, partials,
+                       ntasks, aai, aad, m, active);
 }
 
 void launch_aa_solve(hipStream_t s, int nprob, double *scal, int *aai, double *aad, int m,
                      double reg, double growth, const int *active)
 {
-    hipLaunchKernelGGL(k_aa_solve, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, aai, aad,
-                       m, reg, growth, active);
+    hipLaunchKernelGGL(k_aa_solve, dim3(nprob), dim3(kWave), 0, s, nprob, scal, aai, aad, m, reg,
+                       growth, active);
 }
 
 void launch_aa_update(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
