@@ -184,11 +184,14 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                               best["corr_scale"], nt), best)
     if anderson:
         # phase 3: Anderson windows for the winner, then schedules and
-        # correction factors with the best window
+        # correction factors with the best window.  Anderson acceleration needs
+        # a start near the solution: without grid sequencing in the winner,
+        # its candidates start from the 2:1 coarser solve to 1e-2
         b0 = best
+        nt0 = b0.get("nested_tol", 0.0) or (1e-2 if even else 0.0)
         for m in AA_WINDOWS:
             best = better(run(b0["nu1"], b0["nu2"], b0["omega_s"], b0["restart_growth"],
-                              b0["corr_scale"], b0.get("nested_tol", 0.0), m), best)
+                              b0["corr_scale"], nt0, m), best)
         if best.get("aa_m"):
             b1 = best
             for nu1, nu2, ws in AA_SCHEDULES:
