@@ -55,8 +55,11 @@ AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 
 
-def cache_key(arch: str, shape, precision: str, limiter: str) -> str:
-    return f"{arch}|{shape[0]}x{shape[1]}x{shape[2]}|{precision}|{limiter}"
+def cache_key(arch: str, shape, precision: str, limiter: str, tol: float | None = None) -> str:
+    """Key of a cache entry; ``tol`` names an entry tuned for that tolerance
+    (a schedule that is fastest to 1e-6 need not be to 1e-10)."""
+    key = f"{arch}|{shape[0]}x{shape[1]}x{shape[2]}|{precision}|{limiter}"
+    return key if tol is None else f"{key}|tol={tol:g}"
 
 
 def device_arch(device: int = 0) -> str:
@@ -73,10 +76,14 @@ def load_cache(path: str = CACHE) -> dict:
 
 
 def tuned_options(shape, precision: str = "mixed", limiter: str = "lp", arch: str | None = None,
-                  path: str = CACHE) -> dict:
-    """Cached options for this grid, or {} when it was never tuned."""
+                  path: str = CACHE, tol: float | None = None) -> dict:
+    """Cached options for this grid (with ``tol``: the entry tuned for that
+    tolerance if there is one, else the grid's entry), or {} when it was never
+    tuned."""
     arch = arch or device_arch()
-    entry = load_cache(path).get(cache_key(arch, shape, precision, limiter))
+    cache = load_cache(path)
+    entry = cache.get(cache_key(arch, shape, precision, limiter, tol)) if tol is not None else None
+    entry = entry or cache.get(cache_key(arch, shape, precision, limiter))
     return dict(entry["options"]) if entry else {}
 
 
@@ -100,11 +107,13 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
          probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
          quick: bool = False, refine: bool = False, schedules=None, scales=None,
-         anderson: bool = False) -> dict:
+         anderson: bool = False, tol_key: bool = False) -> dict:
     """Tune one grid/medium; stores and returns the cache entry.  ``schedules``
     ((nu1, nu2, omega_s, restart_growth) tuples) and ``scales`` replace the
     default candidate lists (for grids whose full search is too long).
-    ``anderson`` adds phase 3 (with ``refine``: phase 3 alone)."""
+    ``anderson`` adds phase 3 (with ``refine``: phase 3 alone).  ``tol_key``
+    stores the entry under a key that names ``tol``; ``refine`` then starts
+    from that entry or, if there is none yet, from the grid's own."""
     import torch
 
     import paper_1403_8105_amd as F
@@ -116,8 +125,11 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     ptrs = [t.data_ptr() for t in d]
     base = dict(precision=precision, limiter=limiter)
     even = all(x % 2 == 0 for x in sigma_t.shape)
-    key = cache_key(device_arch(), sigma_t.shape, precision, limiter)
-    old = load_cache(path or CACHE).get(key) if refine else None
+    key = cache_key(device_arch(), sigma_t.shape, precision, limiter, tol if tol_key else None)
+    cache0 = load_cache(path or CACHE)
+    old = cache0.get(key) if refine else None
+    if refine and not old and tol_key:
+        old = cache0.get(cache_key(device_arch(), sigma_t.shape, precision, limiter))
     if refine and not old:
         raise RuntimeError(f"autotune: --refine needs a cached entry for {key}")
 
@@ -172,7 +184,7 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
         for nu1, nu2, ws, gr in cands:
             best = better(run(nu1, nu2, ws, gr, (scales or SCALES)[0]), best)
-    if best is None:
+    if best is None and not (old and anderson):
         raise RuntimeError("autotune: no schedule reached the tolerance")
     if not old:
         for sc in (scales or SCALES)[1:]:
@@ -187,7 +199,12 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         # correction factors with the best window.  Anderson acceleration needs
         # a start near the solution: without grid sequencing in the winner,
         # its candidates start from the 2:1 coarser solve to 1e-2
-        b0 = best
+        # the starting entry's options when none of its runs converged
+        b0 = best or ({k: old["options"].get(k, v) for k, v in
+                       (("nu1", 2), ("nu2", 2), ("omega_s", 1.0), ("restart_growth", 2.0),
+                        ("corr_scale", 1.0), ("nested_tol", 0.0))} if old else None)
+        if b0 is None:
+            raise RuntimeError("autotune: no schedule reached the tolerance")
         nt0 = b0.get("nested_tol", 0.0) or (1e-2 if even else 0.0)
         for m in AA_WINDOWS:
             best = better(run(b0["nu1"], b0["nu2"], b0["omega_s"], b0["restart_growth"],
@@ -208,6 +225,8 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                 best = better(run(b3["nu1"], b3["nu2"], b3["omega_s"], b3["restart_growth"],
                                   b3["corr_scale"], b3.get("nested_tol", 0.0), b3["aa_m"], reg),
                               best)
+    if best is None:
+        raise RuntimeError("autotune: no candidate reached the tolerance")
     opts = {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"], "nu2": best["nu2"],
             "omega_s": best["omega_s"], "restart_growth": best["restart_growth"],
             "corr_scale": best["corr_scale"]}
@@ -223,7 +242,8 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         "ms_to_tol": best["ms"],
         "iterations": best["iterations"],
         "shape_ms_per_iteration": {f"{a},{b}": v for (a, b), v in shape_ms.items()},
-        "schedules": (old.get("schedules", []) if old else []) + results,
+        "schedules": (cache0[key].get("schedules", []) if refine and key in cache0 else [])
+                     + results,
     }
     if path:
         cache = load_cache(path)
@@ -363,6 +383,9 @@ def main(argv=None):
     ap.add_argument("--scales", default=None,
                     help="correction factors 'first,second,...'; the first goes with the "
                          "schedule search (default 1.0,1.2,1.4,1.6,1.8)")
+    ap.add_argument("--tol-key", action="store_true",
+                    help="store the entry under a key naming --tol (a separate entry for a "
+                         "tight tolerance)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from synth import media
@@ -382,7 +405,7 @@ def main(argv=None):
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
                  max_iters=args.max_iters, refine=args.refine, schedules=schedules,
-                 scales=scales, anderson=args.anderson)
+                 scales=scales, anderson=args.anderson, tol_key=args.tol_key)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"]}), flush=True)
 

@@ -88,12 +88,23 @@ struct fld_engine_impl {
     DevList fine_tasks;
     std::vector<int> fine_range;   // host copy, nprob+1
     int *d_fine_range = nullptr;
+    // Anderson dot products: tasks of kAaTaskCells cells, so that each thread
+    // sums several quads before the per-task reduction of its 2(m+1) values
+    DevList aa_tasks;
+    int *d_aa_range = nullptr;
     DevList mid[kMaxLevels], rest[kMaxLevels], gal[kMaxLevels];
     DevList coarse_cells[kMaxLevels];   // every cell of level l+1 (deep levels included)
     int *d_coarse_ids = nullptr, *d_deep_roots = nullptr;   // coarsest grids / deep roots
     int n_coarse = 0, n_deep = 0;
     int *d_tail_roots = nullptr;   // problems whose tail runs in one workgroup launch
     int n_tail = 0;
+    // The coarsest factorisation runs on a second stream (default priority),
+    // forked after the coarse operators are built and joined before the
+    // coarsest solve, beside the down-sweep of the finer levels.
+    int *d_factor_ids = nullptr;   // coarsest grid of every problem
+    int n_factor = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     long long tail_lds = 0;
     int max_coarse_n = 1, max_coarse_bw = 1;
     // kernel instance choice: kmode 0 FP64, 1 FP32 natural, 2 FP32 colour-split,
@@ -284,6 +295,14 @@ struct fld_engine_impl {
     {
         if (stream)
             hipStreamSynchronize(stream);
+        if (side) {
+            hipStreamSynchronize(side);
+            hipStreamDestroy(side);
+        }
+        if (ev_fork)
+            hipEventDestroy(ev_fork);
+        if (ev_join)
+            hipEventDestroy(ev_join);
         for (hipEvent_t e : ev_pool)
             hipEventDestroy(e);
         drop_graphs();
@@ -401,6 +420,8 @@ struct fld_engine_impl {
         std::vector<Fine> hf(nprob);
         std::vector<Task> ft;
         fine_range.assign(nprob + 1, 0);
+        std::vector<Task> at;
+        std::vector<int> aa_range(nprob + 1, 0);
         for (int p = 0; p < nprob; ++p) {
             Prob &P = probs[p];
             P.vol = p / nchan;
@@ -456,6 +477,10 @@ struct fld_engine_impl {
             fine_cells += (double)V.n;
             add_tasks(ft, p, V.n);
             fine_range[p + 1] = (int)ft.size();
+            aa_range[p] = (int)at.size();
+            if (mg && opt.aa_m > 0)
+                add_tasks(at, p, V.n, kAaTaskCells);
+            aa_range[p + 1] = (int)at.size();
             hf[p] = f;
         }
         {
@@ -485,7 +510,12 @@ struct fld_engine_impl {
             CK(dalloc(&d_aai, sizeof(int) * aa_state_ints() * nprob));
             CK(dalloc(&d_aad, sizeof(double) * aa_state_doubles() * nprob));
             HK(hipMemset(d_aad, 0, sizeof(double) * aa_state_doubles() * nprob), "hipMemset");
-            CK(dalloc(&d_aapart, sizeof(double) * 2 * (opt.aa_m + 1) * maxt));
+            CK(upload_list(at, aa_tasks));
+            CK(dalloc(&d_aa_range, sizeof(int) * (nprob + 1)));
+            HK(hipMemcpy(d_aa_range, aa_range.data(), sizeof(int) * (nprob + 1),
+                         hipMemcpyHostToDevice), "hipMemcpy");
+            CK(dalloc(&d_aapart, sizeof(double) * 2 * (opt.aa_m + 1) *
+                                     std::max<size_t>(at.size(), 1)));
         }
         h_active.assign(nprob, 1);
         if (mg)
@@ -523,7 +553,8 @@ struct fld_engine_impl {
                     CK(dalloc(&L.e, tsz * L.n));
                     CK(dalloc(&L.b, tsz * L.n));
                     CK(dalloc(&L.sa, tsz * L.n));
-                    CK(dalloc(&L.f, tsz * 3 * (size_t)(L.nx + 1) * (L.ny + 1) * (L.nz + 1)));
+                    CK(dalloc(&L.f, tsz * 3 * (size_t)(L.nx + 1) * (L.ny + 1) *
+                                        (size_t)face_zstride(L.nz)));
                 }
                 if (l == P.nlev - 1) {
                     const long long W = (long long)L.ny * L.nz + 1;
@@ -613,6 +644,18 @@ struct fld_engine_impl {
             HK(hipMemcpy(d_coarse_ids, coarsest.data(), sizeof(int) * n_coarse,
                          hipMemcpyHostToDevice), "hipMemcpy");
         }
+        {
+            std::vector<int> fids;
+            for (const Prob &P : probs)
+                fids.push_back(P.gid0 + P.nlev - 1);
+            n_factor = (int)fids.size();
+            CK(dalloc(&d_factor_ids, sizeof(int) * n_factor));
+            HK(hipMemcpy(d_factor_ids, fids.data(), sizeof(int) * n_factor,
+                         hipMemcpyHostToDevice), "hipMemcpy");
+            HK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+            HK(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+            HK(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
+        }
         for (int l = 0; l < max_levels; ++l) {
             std::vector<Task> m, r, g, cc;
             // launch shape: task sizes from the cells all problems hold at this level
@@ -624,7 +667,7 @@ struct fld_engine_impl {
                         nm += P.lv[l].n;
                         nr += C.n;
                     }
-                    ng += (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
+                    ng += (long long)(C.nx + 1) * (C.ny + 1) * face_zstride(C.nz);
                 }
             const int tm = l == 0 ? opt.task_cells0 : coarse_task(nm, 512);
             const int tr = coarse_task(nr, 256), tg = coarse_task(ng, 256);
@@ -636,8 +679,8 @@ struct fld_engine_impl {
                         add_tasks(r, P.gid0 + l + 1, P.lv[l + 1].n, tr);
                     }
                     const Level &C = P.lv[l + 1];
-                    add_tasks(g, P.gid0 + l + 1, (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1),
-                              tg);
+                    add_tasks(g, P.gid0 + l + 1,
+                              (long long)(C.nx + 1) * (C.ny + 1) * face_zstride(C.nz), tg);
                     add_tasks(cc, P.gid0 + l + 1, C.n, 256);
                 }
             }
@@ -926,6 +969,11 @@ struct fld_engine_impl {
         for (int l = 0; l + 1 < max_levels; ++l)
             if (gal[l].n)
                 launch_galerkin<T>(stream, G, gal[l].d, gal[l].n, d_active, lsp);
+        // fork: the coarsest factorisations on the second stream
+        note(hipEventRecord(ev_fork, stream), "hipEventRecord");
+        note(hipStreamWaitEvent(side, ev_fork, 0), "hipStreamWaitEvent");
+        launch_coarse_factor<T>(side, G, d_factor_ids, n_factor, d_active, d_fail, max_coarse_n);
+        note(hipEventRecord(ev_join, side), "hipEventRecord");
     }
 
     // One finest-level half-sweep must move, per cell of the grid, the other
@@ -971,6 +1019,8 @@ struct fld_engine_impl {
                 launch_restrict<T>(stream, G, rest[l].d, rest[l].n, d_active, lsp);
             }
         }
+        // join: the coarsest factors are complete
+        note(hipStreamWaitEvent(stream, ev_join, 0), "hipStreamWaitEvent");
         launch_tail<T>(stream, G, d_tail_roots, n_tail, d_active, d_fail, opt.nu1, opt.nu2,
                        opt.omega_s, (int)tail_lds);
         launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.nu1, opt.omega_s, true);
@@ -1070,9 +1120,9 @@ struct fld_engine_impl {
         }
         if (opt.aa_m > 0) {
             const int m = opt.aa_m;
-            launch_aa_dots(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_aai, d_aad, m,
+            launch_aa_dots(stream, d_fines, aa_tasks.d, aa_tasks.n, d_active, d_aai, d_aad, m,
                            d_aapart, kmode);
-            launch_aa_sums(stream, N, d_fine_range, d_aapart, fine_tasks.n, d_aai, d_aad, m,
+            launch_aa_sums(stream, N, d_aa_range, d_aapart, aa_tasks.n, d_aai, d_aad, m,
                            d_active);
             launch_aa_solve(stream, N, d_scal, d_aai, d_aad, m, opt.aa_reg, opt.restart_growth,
                             d_active);

@@ -10,14 +10,21 @@ namespace fld {
 
 constexpr int kBlock = 256;          // threads per block of the work-list kernels
 constexpr int kTaskCells = 4096;     // cells per work-list task
+constexpr int kAaTaskCells = 16384;  // cells per task of the Anderson dot products
 constexpr int kMaxLevels = 16;
 
 // One multigrid level of one problem.  Arrays are z fastest,
 // index (i*ny + j)*nz + k.  The finest level keeps cell coefficients D (its
 // face coefficients follow the discretised equation, (D_p + D_s)/2 with the
 // ghost rule); coarse levels keep Galerkin face coefficients f: three
-// (nx+1)(ny+1)(nz+1) arrays back to back, f[a](i,j,k) = face below (i,j,k)
-// along axis a.
+// (nx+1)(ny+1)(face_zstride(nz)) arrays back to back, f[a](i,j,k) = face
+// below (i,j,k) along axis a; rows along z are padded to a multiple of four
+// entries so that a quad of faces is one aligned 16-byte load.
+__host__ __device__ inline long long face_zstride(int nz)
+{
+    return (long long)((nz + 4) & ~3);     // nz + 1 rounded up to a multiple of 4
+}
+
 struct Grid {
     int nx, ny, nz, prob;
     long long n;
@@ -217,6 +224,13 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
 template <typename T>
 void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
                          const int *active, int *fail, int max_n, int max_bw);
+// Factor of the coarsest operator of each listed grid whose band fits in LDS,
+// into Grid::band (the solve kernels and the tail then substitute only); it
+// reads only the coarse operators, so it may run on a second stream beside the
+// down-sweep.  fail[prob] is set to 1 when a pivot is not positive.
+template <typename T>
+void launch_coarse_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
+                          const int *active, int *fail, int max_n);
 // Coarse tail in one launch per problem (one workgroup each): the deep levels
 // from a root (at most tail_root_cells() cells, then at most tail_max_low()
 // levels of at most tail_low_cells() cells) down to the coarsest solve and

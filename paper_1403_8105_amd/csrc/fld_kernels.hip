@@ -1093,8 +1093,9 @@ __global__ void k_npcg_theta(int nprob, double *scal, const int *active)
 // the last update wrote; the next dots pass adds dF to it), the Gram matrix
 // G_st = dF_s . dF_t and the coefficients.  Per iteration:
 //   k_aa_dots    dF_p = f - f_prev into the pending slot p, dG_p += dF_p,
-//                f_prev = f, and per task the partials of dF_p . dF_s and
-//                dF_s . f for every slot s (dF_p for s = p);
+//                f_prev = f, and per task (kAaTaskCells cells, so a thread
+//                sums several quads before the reduction) the partials of
+//                dF_p . dF_s and dF_s . f for every slot s (dF_p for s = p);
 //   k_aa_sums    per problem those sums in task order;
 //   k_aa_solve   commit p (dropping the oldest when m are held) or, after an
 //                iteration that raised ||r|| by more than restart_growth,
@@ -1108,6 +1109,11 @@ __global__ void k_npcg_theta(int nprob, double *scal, const int *active)
 // ---------------------------------------------------------------------------
 constexpr int kAaMax = 16;                // largest window
 constexpr int kAaSlots = kAaMax + 1;
+// history vectors whose loads a thread issues together, in the dot products
+// and in the update (4 values each in registers): several loads in flight
+// per wave instead of one
+template <typename T>
+constexpr int kAaGroup = sizeof(T) == 4 ? 8 : 4;
 
 // per-problem state: ints [order(kAaSlots), count, pending, pending_valid]
 // and doubles [G (kAaSlots^2), gamma, dots dF_p.dF_s, dots dF_s.f]
@@ -1189,18 +1195,28 @@ k_aa_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active, i
                 st4(fprev + c0, fv);
                 st4(dF + (long long)pnd * n + c0, dn);
                 st4(dGp + c0, gp);
+                // slots in groups whose loads are all issued before any is
+                // consumed, so a wave keeps several history loads in flight
 #pragma unroll
-                for (int s = 0; s < kAaSlots; ++s) {
-                    if (s < W) {
-                        T v[4];
-                        if (s == pnd)
-                            for (int a = 0; a < 4; ++a)
-                                v[a] = dn[a];
-                        else
-                            ld4(dF + (long long)s * n + c0, v);
-                        for (int a = 0; a < 4; ++a) {
-                            g[s] += (double)dn[a] * (double)v[a];
-                            hs[s] += (double)v[a] * (double)fv[a];
+                for (int s0 = 0; s0 < kAaSlots; s0 += kAaGroup<T>) {
+                    T v[kAaGroup<T>][4];
+#pragma unroll
+                    for (int u = 0; u < kAaGroup<T>; ++u) {
+                        const int s = s0 + u;
+                        if (s < kAaSlots && s < W && s != pnd)
+                            ld4(dF + (long long)s * n + c0, v[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kAaGroup<T>; ++u) {
+                        const int s = s0 + u;
+                        if (s < kAaSlots && s < W) {
+                            if (s == pnd)
+                                for (int a = 0; a < 4; ++a)
+                                    v[u][a] = dn[a];
+                            for (int a = 0; a < 4; ++a) {
+                                g[s] += (double)dn[a] * (double)v[u][a];
+                                hs[s] += (double)v[u][a] * (double)fv[a];
+                            }
                         }
                     }
                 }
@@ -1276,7 +1292,11 @@ k_aa_sums(const int *range, const double *partials, int ntasks, int *aai, double
     }
 }
 
-// one block per problem; the first thread solves in LDS
+// one 64-lane block per problem: the first lane commits the pending slot (or
+// clears the history) and picks the next one; the Cholesky factorisation and
+// the forward substitution run right-looking across the lanes, which keeps
+// every entry's subtractions in the order of the column-by-column algorithm
+// (q = 0, 1, ...); the backward substitution is the first lane's
 __global__ void __launch_bounds__(kWave)
 k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m, double reg, double growth,
            const int *active)
@@ -1285,94 +1305,127 @@ k_aa_solve(int nprob, double *scal, int *aai, double *aad, int m, double reg, do
     __shared__ double y[kAaMax];
     __shared__ double Gs[kAaSlots * kAaSlots], dds[kAaSlots], hfs[kAaSlots];
     __shared__ int order[kAaSlots];
+    __shared__ int s_cnt;
+    __shared__ double s_lambda;
     const int p = blockIdx.x;
     if (p >= nprob || (active && !active[p]))
         return;
+    const int tid = threadIdx.x;
     AaView A(aai, aad, p);
-    // the state's doubles into LDS by the whole wavefront, then one lane
-    for (int q = threadIdx.x; q < kAaSlots * kAaSlots; q += blockDim.x)
+    for (int q = tid; q < kAaSlots * kAaSlots; q += blockDim.x)
         Gs[q] = A.G[q];
-    for (int q = threadIdx.x; q < kAaSlots; q += blockDim.x) {
+    for (int q = tid; q < kAaSlots; q += blockDim.x) {
         dds[q] = A.dd[q];
         hfs[q] = A.hf[q];
         order[q] = A.I[q];
     }
     __syncthreads();
-    if (threadIdx.x != 0)
-        return;
     double *sc = scal + p * S_COUNT;
-    int cnt = A.count();
-    const int pnd = A.pending();
-    if (A.pvalid()) {
-        if (growth > 0.0 && sc[S_REL] > growth * sc[S_REL_PREV]) {
-            cnt = 0;                                  // restart: clear the history
-        } else {
-            if (cnt == m) {                           // drop the oldest
-                for (int a = 0; a + 1 < cnt; ++a)
-                    order[a] = order[a + 1];
-                --cnt;
-            }
-            order[cnt++] = pnd;
-            for (int a = 0; a < cnt; ++a) {
-                const int s = order[a];
-                Gs[pnd * kAaSlots + s] = dds[s];
-                Gs[s * kAaSlots + pnd] = dds[s];
-                A.G[pnd * kAaSlots + s] = dds[s];
-                A.G[s * kAaSlots + pnd] = dds[s];
+    if (tid == 0) {
+        int cnt = A.count();
+        const int pnd = A.pending();
+        if (A.pvalid()) {
+            if (growth > 0.0 && sc[S_REL] > growth * sc[S_REL_PREV]) {
+                cnt = 0;                                  // restart: clear the history
+            } else {
+                if (cnt == m) {                           // drop the oldest
+                    for (int a = 0; a + 1 < cnt; ++a)
+                        order[a] = order[a + 1];
+                    --cnt;
+                }
+                order[cnt++] = pnd;
+                for (int a = 0; a < cnt; ++a) {
+                    const int s = order[a];
+                    Gs[pnd * kAaSlots + s] = dds[s];
+                    Gs[s * kAaSlots + pnd] = dds[s];
+                    A.G[pnd * kAaSlots + s] = dds[s];
+                    A.G[s * kAaSlots + pnd] = dds[s];
+                }
             }
         }
-    }
-    sc[S_REL_PREV] = sc[S_REL];
-    for (int s = 0; s < kAaSlots; ++s)
-        A.gam[s] = 0.0;
-    if (cnt > 0) {
-        // (G + lambda I) gamma = h over the committed slots, oldest first
+        sc[S_REL_PREV] = sc[S_REL];
+        for (int s = 0; s < kAaSlots; ++s)
+            A.gam[s] = 0.0;
         double tr = 0.0;
         for (int a = 0; a < cnt; ++a)
             tr += Gs[order[a] * kAaSlots + order[a]];
-        const double lambda = reg * tr / (double)cnt;
-        for (int a = 0; a < cnt; ++a)
-            for (int b = 0; b < cnt; ++b)
-                L[a * kAaMax + b] = Gs[order[a] * kAaSlots + order[b]];
-        for (int a = 0; a < cnt; ++a)
-            L[a * kAaMax + a] = L[a * kAaMax + a] + lambda;
+        s_lambda = cnt > 0 ? reg * tr / (double)cnt : 0.0;
+        s_cnt = cnt;
+    }
+    __syncthreads();
+    int cnt = s_cnt;
+    if (cnt > 0) {
+        // (G + lambda I) gamma = h over the committed slots, oldest first
+        const double lambda = s_lambda;
+        for (int q = tid; q < cnt * cnt; q += blockDim.x) {
+            const int a = q / cnt, b = q - a * cnt;
+            const double g = Gs[order[a] * kAaSlots + order[b]];
+            L[a * kAaMax + b] = a == b ? g + lambda : g;
+        }
+        __syncthreads();
         bool ok = true;
-        for (int c = 0; c < cnt && ok; ++c) {
-            double d = L[c * kAaMax + c];
-            for (int q = 0; q < c; ++q)
-                d = d - L[c * kAaMax + q] * L[c * kAaMax + q];
-            if (!(d > 0.0)) {
+        for (int c = 0; c < cnt; ++c) {
+            const double d = L[c * kAaMax + c];
+            if (!(d > 0.0)) {              // the same value in every lane
                 ok = false;
                 break;
             }
             const double lcc = sqrt(d);
-            L[c * kAaMax + c] = lcc;
-            for (int r = c + 1; r < cnt; ++r) {
-                double s = L[r * kAaMax + c];
-                for (int q = 0; q < c; ++q)
-                    s = s - L[r * kAaMax + q] * L[c * kAaMax + q];
-                L[r * kAaMax + c] = s / lcc;
+            __syncthreads();
+            if (tid == 0)
+                L[c * kAaMax + c] = lcc;
+            for (int r = c + 1 + tid; r < cnt; r += blockDim.x)
+                L[r * kAaMax + c] = L[r * kAaMax + c] / lcc;
+            __syncthreads();
+            // trailing update of the lower triangle: L[r][k] -= L[r][c] L[k][c]
+            const int w = cnt - c - 1;
+            for (int q = tid; q < w * w; q += blockDim.x) {
+                const int r = c + 1 + q / w, k = c + 1 + q % w;
+                if (k <= r)
+                    L[r * kAaMax + k] = L[r * kAaMax + k] - L[r * kAaMax + c] * L[k * kAaMax + c];
             }
+            __syncthreads();
         }
         if (ok) {
+            for (int r = tid; r < cnt; r += blockDim.x)
+                y[r] = hfs[order[r]];
+            __syncthreads();
             for (int r = 0; r < cnt; ++r) {
-                double s = hfs[order[r]];
-                for (int q = 0; q < r; ++q)
-                    s = s - L[r * kAaMax + q] * y[q];
-                y[r] = s / L[r * kAaMax + r];
+                if (tid == 0)
+                    y[r] = y[r] / L[r * kAaMax + r];
+                __syncthreads();
+                for (int q = r + 1 + tid; q < cnt; q += blockDim.x)
+                    y[q] = y[q] - L[q * kAaMax + r] * y[r];
+                __syncthreads();
             }
-            for (int r = cnt - 1; r >= 0; --r) {
-                double s = y[r];
-                for (int q = r + 1; q < cnt; ++q)
-                    s = s - L[q * kAaMax + r] * y[q];
-                y[r] = s / L[r * kAaMax + r];
+            if (tid == 0) {
+                for (int r = cnt - 1; r >= 0; --r) {
+                    double s = y[r];
+                    int q = r + 1;
+                    for (; q + 3 < cnt; q += 4) {
+                        double w[4], v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            w[u] = L[(q + u) * kAaMax + r];
+                            v[u] = y[q + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            s = s - w[u] * v[u];
+                    }
+                    for (; q < cnt; ++q)
+                        s = s - L[q * kAaMax + r] * y[q];
+                    y[r] = s / L[r * kAaMax + r];
+                }
+                for (int a = 0; a < cnt; ++a)
+                    A.gam[order[a]] = y[a];
             }
-            for (int a = 0; a < cnt; ++a)
-                A.gam[order[a]] = y[a];
         } else {
             cnt = 0;
         }
     }
+    if (tid != 0)
+        return;
     A.count() = cnt;
     for (int a = 0; a < cnt; ++a)
         A.I[a] = order[a];
@@ -1433,11 +1486,20 @@ k_aa_update(const Fine *fines, const Task *tasks, int ntasks, const int *active,
                 f_quad<T>(f, sp, dec, c0, fv);
                 for (int a = 0; a < 4; ++a)
                     step[a] = (double)fv[a];
-                for (int a = 0; a < cnt; ++a) {
-                    T v[4];
-                    ld4(dG + (long long)ord[a] * n + c0, v);
-                    for (int b = 0; b < 4; ++b)
-                        step[b] = step[b] - gm[a] * (double)v[b];
+                // history slots oldest first, in groups whose loads are all
+                // issued before any is consumed
+#pragma unroll
+                for (int a0 = 0; a0 < kAaMax; a0 += kAaGroup<T>) {
+                    T v[kAaGroup<T>][4];
+#pragma unroll
+                    for (int u = 0; u < kAaGroup<T>; ++u)
+                        if (a0 + u < kAaMax && a0 + u < cnt)
+                            ld4(dG + (long long)ord[a0 + u] * n + c0, v[u]);
+#pragma unroll
+                    for (int u = 0; u < kAaGroup<T>; ++u)
+                        if (a0 + u < kAaMax && a0 + u < cnt)
+                            for (int b = 0; b < 4; ++b)
+                                step[b] = step[b] - gm[a0 + u] * (double)v[u][b];
                 }
                 ld4(x + c0, xv);
                 for (int b = 0; b < 4; ++b) {
@@ -1468,7 +1530,7 @@ k_aa_update(const Fine *fines, const Task *tasks, int ntasks, const int *active,
 
 __device__ inline long long fidx(const Grid &g, int i, int j, int k)
 {
-    return ((long long)i * (g.ny + 1) + j) * (g.nz + 1) + k;
+    return ((long long)i * (g.ny + 1) + j) * face_zstride(g.nz) + k;
 }
 
 // Face coefficient below cell (i,j,k) along axis ax (either side may be a
@@ -1485,7 +1547,7 @@ template <typename T>
 __device__ inline T face_below(const Grid &g, int ax, int i, int j, int k, bool sp = false)
 {
     if (!g.fine) {
-        const long long nf = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+        const long long nf = (long long)(g.nx + 1) * (g.ny + 1) * face_zstride(g.nz);
         return ((const T *)g.f)[ax * nf + fidx(g, i, j, k)];
     }
     const T *D = (const T *)g.D;
@@ -1547,7 +1609,7 @@ __device__ inline void face_num_den(const Grid &g, const T *e, long long c, int 
 {
     const T h2 = (T)g.h2;
     const long long sx = (long long)g.ny * g.nz, sy = g.nz;
-    const long long fy = (long long)(g.nz + 1), fx = (long long)(g.ny + 1) * fy;
+    const long long fy = face_zstride(g.nz), fx = (long long)(g.ny + 1) * fy;
     const long long nf = (long long)(g.nx + 1) * fx;
     const long long fi = (long long)i * fx + (long long)j * fy + k;
     const T *__restrict__ Fx = (const T *)g.f;
@@ -1617,9 +1679,9 @@ k_zero(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 // dimensions; a task's cells pair up along z and each thread updates the
 // cell of the requested colour in its pair.
 // Red-black half-sweep of the level smoother.  The finest level (cell D,
-// face coefficients formed on the fly) and the coarse levels (stored Galerkin
-// faces) are separate kernels, so profiles can tell them apart.
-template <typename T>
+// face coefficients formed on the fly; FINE) and the coarse levels (stored
+// Galerkin faces) are separate kernels, each compiled with its own paths only.
+template <typename T, bool FINE>
 __device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *tasks, int ntasks,
                                              const int *active, int colour, T omega)
 {
@@ -1631,7 +1693,7 @@ __device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *task
         T *e = (T *)g.e;
         const Dec dec(g.ny, g.nz);
         const int npairs = tk.count >> 1;
-        if (g.split) {
+        if (FINE && g.split) {
             // colour-split finest level: the task's cells of this colour are
             // the compact run [start/2, (start+count)/2); a thread updates 4
             // of them (8 cells of one z row, k0 % 8 == 0), one 16-byte run of
@@ -1729,7 +1791,7 @@ __device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *task
                 }
                 st4(e + so, out);
             }
-        } else if (g.fine && (g.nz & 3) == 0) {
+        } else if (FINE && (g.nz & 3) == 0) {
             const T *__restrict__ D = (const T *)g.D;
             const T *__restrict__ bb = (const T *)g.b;
             const T *__restrict__ sa = (const T *)g.sa;
@@ -1769,7 +1831,7 @@ __device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *task
                 }
                 st4(e + c0, out);
             }
-        } else if (g.fine) {
+        } else if (FINE) {
             for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
                 const long long c0 = tk.start + 2 * (long long)q;
                 int i, j, k;
@@ -1779,6 +1841,69 @@ __device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *task
                 T num, den;
                 cell_num_den<T>(g, e, c, i, j, k + odd, num, den);
                 e[c] = omega * (num / den) + ((T)1 - omega) * e[c];
+            }
+        } else if ((g.nz & 3) == 0 && (tk.count & 3) == 0) {
+            // coarse level, four cells along z per thread (two of this
+            // colour): 16-byte loads of e, b, sa and of the x and y face
+            // quads, the z faces as a quad plus one; per cell the arithmetic
+            // and its order are those of face_num_den
+            const T *__restrict__ bb = (const T *)g.b;
+            const T *__restrict__ sa = (const T *)g.sa;
+            const long long sx = (long long)g.ny * g.nz, sy = g.nz;
+            const long long fy = face_zstride(g.nz), fx = (long long)(g.ny + 1) * fy;
+            const long long nf = (long long)(g.nx + 1) * fx;
+            const T *__restrict__ Fx = (const T *)g.f;
+            const T *__restrict__ Fy = Fx + nf;
+            const T *__restrict__ Fz = Fy + nf;
+            const T h2 = (T)g.h2;
+            auto E4 = [&](long long x, T v[4]) { ld4(e + x, v); };
+            auto E1 = [&](long long x) { return e[x]; };
+            for (int q = threadIdx.x; q < (tk.count >> 2); q += blockDim.x) {
+                const long long c0 = tk.start + 4 * (long long)q;
+                int i, j, k0;
+                dec(c0, i, j, k0);
+                Hood<T> Eh;
+                gather(Eh, E4, E1, c0, i, j, k0, g.nx, g.ny, g.nz, sx, sy, (T)0);
+                const long long fi = (long long)i * fx + (long long)j * fy + k0;
+                T fxm[4], fxp[4], fym[4], fyp[4], fz[4], bq[4], saq[4], out[4];
+                ld4(Fx + fi, fxm);
+                ld4(Fx + fi + fx, fxp);
+                ld4(Fy + fi, fym);
+                ld4(Fy + fi + fy, fyp);
+                ld4(Fz + fi, fz);
+                const T fz4 = Fz[fi + 4];
+                ld4(bb + c0, bq);
+                ld4(sa + c0, saq);
+                const int first = (i + j + colour) & 1;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    out[m] = Eh.c[m];
+                    if ((m & 1) != first)
+                        continue;
+                    T n_ = bq[m] * h2;
+                    T d_ = saq[m] * h2;
+                    T F;
+                    F = fxm[m];
+                    n_ = n_ + F * Eh.xm[m];
+                    d_ = d_ + F;
+                    F = fxp[m];
+                    n_ = n_ + F * Eh.xp[m];
+                    d_ = d_ + F;
+                    F = fym[m];
+                    n_ = n_ + F * Eh.ym[m];
+                    d_ = d_ + F;
+                    F = fyp[m];
+                    n_ = n_ + F * Eh.yp[m];
+                    d_ = d_ + F;
+                    F = fz[m];
+                    n_ = n_ + F * Eh.zm(m);
+                    d_ = d_ + F;
+                    F = m < 3 ? fz[m + 1] : fz4;
+                    n_ = n_ + F * Eh.zp(m);
+                    d_ = d_ + F;
+                    out[m] = omega * (n_ / d_) + ((T)1 - omega) * Eh.c[m];
+                }
+                st4(e + c0, out);
             }
         } else {
             for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
@@ -1800,14 +1925,14 @@ __global__ void __launch_bounds__(kBlock)
 k_smooth_fine(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour,
               T omega)
 {
-    smooth_tasks<T>(grids, tasks, ntasks, active, colour, omega);
+    smooth_tasks<T, true>(grids, tasks, ntasks, active, colour, omega);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour, T omega)
 {
-    smooth_tasks<T>(grids, tasks, ntasks, active, colour, omega);
+    smooth_tasks<T, false>(grids, tasks, ntasks, active, colour, omega);
 }
 
 // Coarse right-hand side = 8-child mean of the fine residual b - A e.
@@ -1935,7 +2060,7 @@ k_prolong(const Grid *grids, const Task *tasks, int ntasks, const int *active, d
 
 // Galerkin coarse faces: half the sum of the four fine faces on each coarse
 // face (in-face indices in lexicographic order).  Tasks run over the padded
-// (nx+1)(ny+1)(nz+1) face grid of the coarse level.
+// (nx+1)(ny+1)(face_zstride(nz)) face grid of the coarse level.
 template <typename T, int SP>
 __global__ void __launch_bounds__(kBlock)
 k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
@@ -1948,8 +2073,9 @@ k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         const Grid &F = grids[C.finer];
         const bool sp = grid_split<SP>(F);
         T *fc = (T *)C.f;
-        const long long nf = (long long)(C.nx + 1) * (C.ny + 1) * (C.nz + 1);
-        const Dec dec(C.ny + 1, C.nz + 1);
+        // tasks run over the padded face grid; padding entries get zeros
+        const long long nf = (long long)(C.nx + 1) * (C.ny + 1) * face_zstride(C.nz);
+        const Dec dec(C.ny + 1, (int)face_zstride(C.nz));
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int I, J, K;
@@ -1976,7 +2102,7 @@ k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
             }
             fc[nf + c] = v;
             v = (T)0;
-            if (I < C.nx && J < C.ny) {
+            if (I < C.nx && J < C.ny && K <= C.nz) {
                 T s = (T)0;
                 s = s + face_below<T>(F, 2, 2 * I, 2 * J, 2 * K, sp);
                 s = s + face_below<T>(F, 2, 2 * I, 2 * J + 1, 2 * K, sp);
@@ -2202,17 +2328,124 @@ __device__ bool chol_band(double *__restrict__ W, double *__restrict__ diag,
     }
     if (tid == 0) {
         y[n - 1] = y[n - 1] / diag[n - 1];     // the forward substitution's last row
-        // L^T x = y, row by row, subtractions in ascending order
+        // L^T x = y, row by row, subtractions in ascending order; the band and
+        // y entries of four subtractions are loaded before the first of them
         for (int r = n - 1; r >= 0; --r) {
             const int m = min(bw, n - 1 - r);
             double s = y[r];
-            for (int a = 1; a <= m; ++a)
+            int a = 1;
+            for (; a + 3 <= m; a += 4) {
+                double w[4], v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    w[u] = W[(long long)(r + a + u) * Wd + r - (r + a + u) + bw];
+                    v[u] = y[r + a + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    s = s - w[u] * v[u];
+            }
+            for (; a <= m; ++a)
                 s = s - W[(long long)(r + a) * Wd + r - (r + a) + bw] * y[r + a];
             y[r] = s / diag[r];
         }
     }
     __syncthreads();
     return !bad;
+}
+
+// Factorisation alone, as chol_band does it (the same operations in the same
+// order, the right-hand side left out); the factor's diagonal goes to diag.
+__device__ bool chol_factor(double *__restrict__ W, double *__restrict__ diag, int n, int bw)
+{
+    const int Wd = bw + 1;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    bool bad = false;
+    for (int c = 0; c < n; ++c) {
+        const double d = W[(long long)c * Wd + bw];
+        bad = bad || !(d > 0.0);
+        const double lcc = sqrt(d);
+        if (c > 0) {
+            const double lp = diag[c - 1];
+            const int mp = min(bw, n - c);
+            for (int a = tid; a < mp; a += nt) {
+                double &w = W[(long long)(c + a) * Wd + (c - 1) - (c + a) + bw];
+                w = w / lp;
+            }
+        }
+        if (tid == 0)
+            diag[c] = lcc;
+        const int m = min(bw, n - 1 - c);
+        for (int x = tid; x < m * m; x += nt) {
+            const int a = x / m, bb = x - a * m;
+            if (bb > a)
+                continue;
+            const int r = c + 1 + a, q = c + 1 + bb;
+            const double lrc = W[(long long)r * Wd + c - r + bw] / lcc;
+            const double lqc = W[(long long)q * Wd + c - q + bw] / lcc;
+            double &tt = W[(long long)r * Wd + q - r + bw];
+            tt = tt - lrc * lqc;
+        }
+        __syncthreads();
+    }
+    return !bad;
+}
+
+// Ordering of one wavefront's own LDS accesses across lanes (no workgroup
+// barrier): what a lane wrote before is seen by every lane after.
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// L L^T x = y with the factor of chol_factor in W (in LDS; its diagonal in
+// the diagonal slots), by the 64 lanes of one wavefront: the forward
+// substitution right-looking across the lanes, the backward substitution in
+// the first lane.  Each y entry receives its subtractions in the order of
+// chol_band (ascending columns forward, ascending rows backward), so the
+// result is the same.  The other wavefronts must not touch W or y until a
+// barrier after the call.
+__device__ void chol_solve_wave(const double *__restrict__ W, double *__restrict__ y, int n,
+                                int bw)
+{
+    const int Wd = bw + 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int c = 0; c < n; ++c) {
+        if (lane == 0)
+            y[c] = y[c] / W[(long long)c * Wd + bw];
+        wave_lds_sync();
+        const double yc = y[c];
+        const int m = min(bw, n - 1 - c);
+        for (int a = lane; a < m; a += kWave) {
+            const int r = c + 1 + a;
+            y[r] = y[r] - W[(long long)r * Wd + c - r + bw] * yc;
+        }
+        wave_lds_sync();
+    }
+    if (lane == 0) {
+        for (int r = n - 1; r >= 0; --r) {
+            const int m = min(bw, n - 1 - r);
+            double s = y[r];
+            int a = 1;
+            for (; a + 7 <= m; a += 8) {
+                double w[8], v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    w[u] = W[(long long)(r + a + u) * Wd + r - (r + a + u) + bw];
+                    v[u] = y[r + a + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    s = s - w[u] * v[u];
+            }
+            for (; a <= m; ++a)
+                s = s - W[(long long)(r + a) * Wd + r - (r + a) + bw] * y[r + a];
+            y[r] = s / W[(long long)r * Wd + bw];
+        }
+    }
+    wave_lds_sync();
 }
 
 // Rows of M = h^2 A for the coarsest grid g into the band W (one row per
@@ -2261,6 +2494,42 @@ __host__ __device__ inline bool chol_in_lds(long long n, long long bw, long long
     return n * (bw + 1) * 8 + 2 * max_n * 8 <= kCholLds;
 }
 
+// Factor of the coarsest operator, one block per coarsest grid whose band
+// fits in LDS: M = h^2 A assembled into LDS, factored (chol_factor) and stored
+// in g.band with the factor's diagonal in the diagonal slots.  It depends only
+// on the coarse operators, so it runs beside the down-sweep of the finer
+// levels; the solve kernels then only substitute.  fail[prob] is set to 1 when
+// a pivot is not positive.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_coarse_factor(const Grid *grids, const int *ids, const int *active, int *fail, int max_n)
+{
+    extern __shared__ double lds[];
+    const Grid &g = grids[ids[blockIdx.x]];
+    if (active && !active[g.prob])
+        return;
+    (void)max_n;
+    const int n = (int)g.n, bw = g.ny * g.nz, Wd = bw + 1;
+    if (!chol_in_lds(n, bw, n))
+        return;                                // factored by k_coarse_solve itself
+    double *diag = lds + n;
+    double *W = lds + 2 * n;
+    chol_assemble<T>(g, W);
+    __syncthreads();
+    const bool ok = chol_factor(W, diag, n, bw);
+    __syncthreads();
+    for (int x = threadIdx.x; x < n * Wd; x += blockDim.x) {
+        const int r = x / Wd;
+        g.band[x] = x - r * Wd == bw ? diag[r] : W[x];
+    }
+    if (threadIdx.x == 0 && !ok)
+        fail[g.prob] = 1;
+}
+
+// Coarsest solve, one block per listed grid: with the factor of
+// k_coarse_factor (copied into LDS) the two substitutions by one wavefront;
+// a band too large for LDS is assembled, factored and solved here in global
+// memory (chol_band).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, int max_n)
@@ -2269,17 +2538,27 @@ k_coarse_solve(const Grid *grids, const int *ids, const int *active, int *fail, 
     const Grid &g = grids[ids[blockIdx.x]];
     if (active && !active[g.prob])
         return;
-    const int n = (int)g.n, bw = g.ny * g.nz;
-    double *y = lds, *diag = lds + max_n;
-    double *W = chol_in_lds(n, bw, max_n) ? lds + 2 * max_n : g.band;
+    (void)max_n;
+    const int n = (int)g.n, bw = g.ny * g.nz, Wd = bw + 1;
+    double *y = lds, *diag = lds + n;
     const T *b = (const T *)g.b;
-    chol_assemble<T>(g, W);
     for (int r = threadIdx.x; r < n; r += blockDim.x)
         y[r] = (double)b[r] * g.h2;
-    __syncthreads();
-    const bool ok = chol_band(W, diag, y, n, bw);
-    if (threadIdx.x == 0 && !ok)
-        fail[g.prob] = 1;
+    if (chol_in_lds(n, bw, n)) {
+        double *W = lds + 2 * n;
+        for (int x = threadIdx.x; x < n * Wd; x += blockDim.x)
+            W[x] = g.band[x];
+        __syncthreads();
+        if (threadIdx.x < kWave)
+            chol_solve_wave(W, y, n, bw);
+        __syncthreads();
+    } else {
+        chol_assemble<T>(g, g.band);
+        __syncthreads();
+        const bool ok = chol_band(g.band, diag, y, n, bw);
+        if (threadIdx.x == 0 && !ok)
+            fail[g.prob] = 1;
+    }
     T *e = (T *)g.e;
     for (int r = threadIdx.x; r < n; r += blockDim.x)
         e[r] = (T)y[r];
@@ -2317,7 +2596,7 @@ __device__ inline void tail_coef(const Grid &g, long long c, int i, int j, int k
                                  bool with_b)
 {
     const T h2 = (T)g.h2;
-    const long long fy = (long long)(g.nz + 1), fx = (long long)(g.ny + 1) * fy;
+    const long long fy = face_zstride(g.nz), fx = (long long)(g.ny + 1) * fy;
     const long long nf = (long long)(g.nx + 1) * fx;
     const long long fi = (long long)i * fx + (long long)j * fy + k;
     const T *Fx = (const T *)g.f;
@@ -2479,7 +2758,9 @@ k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail,
         tail_load<T, 1>(grids[lv[1]], q1, false);
     if (nd >= 3)
         tail_load<T, 1>(grids[lv[2]], q2, false);
-    chol_assemble<T>(Cg, W);
+    // the coarsest factor (k_coarse_factor) into LDS
+    for (int x = threadIdx.x; x < nc * (bw + 1); x += kTailBlock)
+        W[x] = Cg.band[x];
     if (nd == 0)
         for (int c = threadIdx.x; c < nc; c += kTailBlock)
             y[c] = (double)((const T *)Cg.b)[c] * Cg.h2;
@@ -2522,9 +2803,9 @@ k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail,
     }
     // coarsest (the band, y and the level data written above are complete)
     __syncthreads();
-    const bool ok = chol_band(W, diag, y, nc, bw);
-    if (threadIdx.x == 0 && !ok)
-        fail[Cg.prob] = 1;
+    if (threadIdx.x < kWave)
+        chol_solve_wave(W, y, nc, bw);
+    __syncthreads();
     if (nd == 0) {
         T *ec = (T *)Cg.e;
         for (int c = threadIdx.x; c < nc; c += kTailBlock)
@@ -2841,6 +3122,14 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
 }
 
 template <typename T>
+void launch_coarse_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
+                          const int *active, int *fail, int max_n)
+{
+    if (count > 0)
+        hipLaunchKernelGGL(k_coarse_factor<T>, dim3(count), dim3(kBlock), kCholLds, s, grids, ids,
+                           active, fail, max_n);
+}
+template <typename T>
 void launch_tail(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
                  int *fail, int nu1, int nu2, double omega, int lds_bytes)
 {
@@ -2883,7 +3172,9 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
     template void launch_deep<T>(hipStream_t, const Grid *, const int *, int, const int *, int,  \
                                  double, bool);                                                  \
     template void launch_tail<T>(hipStream_t, const Grid *, const int *, int, const int *, int *,  \
-                                 int, int, double, int);
+                                 int, int, double, int);                                         \
+    template void launch_coarse_factor<T>(hipStream_t, const Grid *, const int *, int,           \
+                                          const int *, int *, int);
 
 FLD_INSTANTIATE(float)
 FLD_INSTANTIATE(double)
