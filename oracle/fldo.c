@@ -49,6 +49,12 @@
  *                                  linearity; product form of the transmittance
  */
 #include <math.h>
+
+/* Loops over fewer cells than this run on one thread: every loop writes each
+ * cell independently (no reductions), so the thread count changes no result,
+ * only the overhead of starting threads for the small grids of the tests and
+ * the coarse levels. */
+#define FLDO_PARALLEL(cells) ((cells) >= 65536L)
 #include <stdlib.h>
 #include <string.h>
 
@@ -218,7 +224,7 @@ static double d_update_at(const fldo_params *p, const double *phi, const double 
 
 void fldo_knudsen(const fldo_params *p, const double *phi, const double *sig_hat, double *R)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)p->nx * p->ny * p->nz))
     for (int i = 0; i < p->nx; ++i)
         for (int j = 0; j < p->ny; ++j)
             for (int k = 0; k < p->nz; ++k)
@@ -228,7 +234,7 @@ void fldo_knudsen(const fldo_params *p, const double *phi, const double *sig_hat
 /* Limiter pass: every D_p from the same fluence field. */
 void fldo_limiter_pass(const fldo_params *p, const double *phi, const double *sig_hat, double *D)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)p->nx * p->ny * p->nz))
     for (int i = 0; i < p->nx; ++i)
         for (int j = 0; j < p->ny; ++j)
             for (int k = 0; k < p->nz; ++k)
@@ -269,7 +275,7 @@ double fldo_residual(const fldo_params *p, const double *phi, const double *D,
     long n = (long)p->nx * p->ny * p->nz;
     double h2 = p->h * p->h;
     double *rr = r ? r : (double *)malloc(sizeof(double) * n);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)p->nx * p->ny * p->nz))
     for (int i = 0; i < p->nx; ++i)
         for (int j = 0; j < p->ny; ++j)
             for (int k = 0; k < p->nz; ++k) {
@@ -313,7 +319,7 @@ static void alg1_pass(const fldo_params *p, double omega, int colour, double *ph
                       double *Rsq)
 {
     double h2 = p->h * p->h;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)p->nx * p->ny * p->nz))
     for (int i = 0; i < p->nx; ++i)
         for (int j = 0; j < p->ny; ++j)
             for (int k = 0; k < p->nz; ++k) {
@@ -449,7 +455,7 @@ static void level_num_den(const mg_level *L, double d_ghost, int mirror, const d
 static void level_smooth_colour(mg_level *L, double d_ghost, int mirror, int colour,
                                 double omega_s)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)L->nx * L->ny * L->nz))
     for (int i = 0; i < L->nx; ++i)
         for (int j = 0; j < L->ny; ++j)
             for (int k = 0; k < L->nz; ++k) {
@@ -466,7 +472,7 @@ static void level_smooth_colour(mg_level *L, double d_ghost, int mirror, int col
 static void level_residual(const mg_level *L, double d_ghost, int mirror, double *r)
 {
     double h2 = L->h * L->h;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)L->nx * L->ny * L->nz))
     for (int i = 0; i < L->nx; ++i)
         for (int j = 0; j < L->ny; ++j)
             for (int k = 0; k < L->nz; ++k) {
@@ -481,7 +487,7 @@ static void level_residual(const mg_level *L, double d_ghost, int mirror, double
 static void level_apply(const mg_level *L, double d_ghost, int mirror, const double *x, double *out)
 {
     double h2 = L->h * L->h;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)L->nx * L->ny * L->nz))
     for (int i = 0; i < L->nx; ++i)
         for (int j = 0; j < L->ny; ++j)
             for (int k = 0; k < L->nz; ++k) {
@@ -495,7 +501,7 @@ static void level_apply(const mg_level *L, double d_ghost, int mirror, const dou
 /* Mean over the 8 children, children visited with x slowest, z fastest. */
 static void mean8(int nxc, int nyc, int nzc, int nyf, int nzf, const double *fine, double *coarse)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)nxc * nyc * nzc))
     for (int I = 0; I < nxc; ++I)
         for (int J = 0; J < nyc; ++J)
             for (int K = 0; K < nzc; ++K) {
@@ -539,7 +545,7 @@ static void galerkin_faces(const mg_level *F, mg_level *C, double d_ghost, int m
 /* e_fine += P e_coarse: every fine cell receives its parent's value. */
 static void prolong_add(const mg_level *C, mg_level *F, double scale)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)F->nx * F->ny * F->nz))
     for (int i = 0; i < F->nx; ++i)
         for (int j = 0; j < F->ny; ++j)
             for (int k = 0; k < F->nz; ++k) {
@@ -1198,7 +1204,7 @@ int fldo_solve(const fldo_params *p, const fldo_solve_opts *o, const double *sig
 void fldo_light_bake(int nx, int ny, int nz, double h, double light, const double *sigma_t,
                      const double *albedo, double *q)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)nx * ny * nz))
     for (int i = 0; i < nx; ++i)
         for (int j = 0; j < ny; ++j) {
             double tau = 0.0;                    /* sum of sigma_t over k' < k */
@@ -1229,7 +1235,7 @@ void fldo_render(int nx, int ny, int nz, double h, double background, const doub
                  const double *albedo, const double *src, const double *phi, double *image)
 {
     const double four_pi = 4.0 * 3.14159265358979323846;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (FLDO_PARALLEL((long)nx * ny * nz))
     for (int i = 0; i < nx; ++i)
         for (int j = 0; j < ny; ++j) {
             double tau = 0.0;                    /* sum of sigma_t over k' > k */
