@@ -146,6 +146,13 @@ typedef struct fld_options {
                              grid sequencing keeps the default step                        */
     double aa_reg;        /* Anderson: Tikhonov weight relative to the mean diagonal of the
                              Gram matrix of correction differences (default 1e-10)          */
+    int fuse_lr;          /* multigrid: 1 forms D and the residual of the finest level in
+                             one pass over LDS tiles when every grid has nz % 4 == 0 and
+                             no direction update is pending (Anderson steps, and the first
+                             iteration of a call); 0 (default) uses the separate limiter
+                             and residual passes, which are faster with the LP limiter on
+                             MI355X.  D and r are the same either way; only the grouping
+                             of the partial sums of the residual norm differs               */
 } fld_options;
 
 typedef struct fld_report {

@@ -92,6 +92,12 @@ struct fld_engine_impl {
     // sums several quads before the per-task reduction of its 2(m+1) values
     DevList aa_tasks;
     int *d_aa_range = nullptr;
+    // fused limiter-residual pass: tiles of every problem, problem by problem
+    bool fuse = false;
+    LrTile *d_lrtiles = nullptr;
+    int n_lrtiles = 0;
+    int *d_lr_range = nullptr;
+    double *d_lrpart = nullptr;
     DevList mid[kMaxLevels], rest[kMaxLevels], gal[kMaxLevels];
     DevList coarse_cells[kMaxLevels];   // every cell of level l+1 (deep levels included)
     int *d_coarse_ids = nullptr, *d_deep_roots = nullptr;   // coarsest grids / deep roots
@@ -491,6 +497,30 @@ struct fld_engine_impl {
             kmode = !mixed ? 0 : lsp + 1;
         }
         CK(upload_list(ft, fine_tasks));
+        fuse = mg && opt.fuse_lr != 0;
+        for (int p = 0; p < nprob; ++p)
+            fuse = fuse && hf[p].nz % 4 == 0;
+        if (fuse) {
+            std::vector<LrTile> lt;
+            std::vector<int> lr_range(nprob + 1, 0);
+            for (int p = 0; p < nprob; ++p) {
+                const Fine &f = hf[p];
+                lr_range[p] = (int)lt.size();
+                for (int i0 = 0; i0 < f.nx; i0 += kLrTilePlanes)
+                    for (int j0 = 0; j0 < f.ny; j0 += kLrTileRows)
+                        for (int k0 = 0; k0 < f.nz; k0 += kLrTileCells)
+                            lt.push_back(LrTile{p, i0, std::min(kLrTilePlanes, f.nx - i0), j0, k0});
+                lr_range[p + 1] = (int)lt.size();
+            }
+            n_lrtiles = (int)lt.size();
+            CK(dalloc(&d_lrtiles, sizeof(LrTile) * lt.size()));
+            HK(hipMemcpy(d_lrtiles, lt.data(), sizeof(LrTile) * lt.size(), hipMemcpyHostToDevice),
+               "hipMemcpy");
+            CK(dalloc(&d_lr_range, sizeof(int) * (nprob + 1)));
+            HK(hipMemcpy(d_lr_range, lr_range.data(), sizeof(int) * (nprob + 1),
+                         hipMemcpyHostToDevice), "hipMemcpy");
+            CK(dalloc(&d_lrpart, sizeof(double) * lt.size()));
+        }
         CK(dalloc(&d_fine_range, sizeof(int) * (nprob + 1)));
         HK(hipMemcpy(d_fine_range, fine_range.data(), sizeof(int) * (nprob + 1),
                      hipMemcpyHostToDevice), "hipMemcpy");
@@ -1083,6 +1113,17 @@ struct fld_engine_impl {
         // with Anderson acceleration the update pass has written phi^k already
         if (opt.aa_m > 0)
             first = true;
+        if (first && fuse) {
+            // D (FP64 as well when a conjugate-direction pass will read it) and
+            // r in one pass; phi, sig_hat, sa, j read
+            const bool d64 = !mixed || opt.aa_m == 0;
+            launch_lim_res(stream, d_fines, d_lrtiles, n_lrtiles, d_active, d_scal, k & 1, k & 1,
+                           d64 ? 1 : 0, d_lrpart, kmode);
+            toc(ta, 1, 32.0 + tsz + (mixed ? 4.0 : 0.0) + (d64 ? 8.0 : 0.0));
+            launch_sum_partials(stream, N, d_lr_range, d_lrpart, d_scal, S_RES2, d_active);
+            launch_rel(stream, N, d_scal, d_active);
+            return;
+        }
         if (first)
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
                            k & 1, 0, 0, 0, kmode);
@@ -1406,6 +1447,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->nested_tol > 0.0 && o->method != FLD_METHOD_MG) { err = "nested_tol needs the multigrid method"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->nested_tol > 0.0 && o->anisotropy_g != 0.0) { err = "nested_tol needs anisotropy_g = 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->aa_m < 0 || o->aa_m > aa_max_window()) { err = "aa_m must lie in [0,16]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->fuse_lr != 0 && o->fuse_lr != 1) { err = "fuse_lr must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->aa_reg >= 0.0 && std::isfinite(o->aa_reg))) { err = "aa_reg must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
@@ -1519,6 +1561,7 @@ fld_status fld_default_options(fld_options *o)
     o->nested_tol = 0.0;
     o->aa_m = 0;
     o->aa_reg = 1e-10;
+    o->fuse_lr = 0;
     return FLD_OK;
 }
 

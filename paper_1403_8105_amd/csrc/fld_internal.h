@@ -77,6 +77,16 @@ struct Fine {
     void *aa_fprev, *aa_dF, *aa_dG;
 };
 
+// A tile of the fused limiter-residual pass: planes [i0, i0+ni) of rows
+// [j0, j0+16) and cells [k0, k0+32) along z (clipped to the grid) of problem
+// `prob`.
+struct LrTile {
+    int prob;
+    int i0, ni;
+    int j0, k0;
+};
+constexpr int kLrTileRows = 16, kLrTileCells = 32, kLrTilePlanes = 32;
+
 // A run of cluster voxels: entries [start, start+count) of the problem's
 // cpos (cell tasks) or rcells (rim tasks) list, all in global cluster `cl`.
 struct CTask {
@@ -228,6 +238,13 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
 // into Grid::band (the solve kernels and the tail then substitute only); it
 // reads only the coarse operators, so it may run on a second stream beside the
 // down-sweep.  fail[prob] is set to 1 when a pivot is not positive.
+// Limiter and residual of the finest level in one pass over LrTile tiles
+// (grids with nz % 4 == 0): D (precision T; also FP64 when write_d64), r in
+// b0[b0_idx] (precision T) and one partial sum of r^2 per tile; the same D and
+// r as launch_limiter (without the direction update) + launch_residual.
+void launch_lim_res(hipStream_t s, const Fine *fines, const LrTile *tiles, int ntiles,
+                    const int *active, const double *scal, int src, int b0_idx, int write_d64,
+                    double *partials, int mixed);
 template <typename T>
 void launch_coarse_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
                           const int *active, int *fail, int max_n);

@@ -603,6 +603,235 @@ k_npcg_dots(const Fine *fines, const Task *tasks, int ntasks, const int *active,
     }
 }
 
+// Limiter and residual in one pass (Sec. 5: gradient, Knudsen number and
+// D update, then the residual with those D).  A block marches along x through
+// a tile of kLrTy rows by kLrTz cells along z, keeping four planes of phi
+// (two-cell halo, ghosts phi_b) and three planes of D (one-cell halo) in LDS.
+// Step x forms D(x+1) on the tile and its halo, then the residual of plane x
+// from LDS; the global loads of the next step (phi(x+3), sig_hat(x+2)) and
+// this step's j and sa are issued at its start, so their latency is spent
+// under the arithmetic.  sig_hat of a plane waits in the LDS slot its D will
+// take (each thread reads it and writes the D of the same cell).  Per cell the
+// arithmetic and its order are those of k_limiter and k_residual, so D and r
+// are identical to theirs; only the partial sums of r^2 (one per tile) are
+// grouped differently.  A halo D is formed by every tile that needs it.
+// Writes r and D in precision T (D also in FP64 when write_d64) for the
+// tile's own cells.  Needs nz % 4 == 0.
+constexpr int kLrTy = kLrTileRows, kLrTz = kLrTileCells;
+constexpr int kLrThreads = kLrTy * kLrTz / 4;          // one quad per thread
+constexpr int kLrPy = kLrTy + 4, kLrPz = kLrTz + 4;    // phi planes
+constexpr int kLrDy = kLrTy + 2, kLrDz = kLrTz + 2;    // D planes
+constexpr int kLrPf = (kLrPy * kLrPz + kLrThreads - 1) / kLrThreads;   // phi values per thread
+constexpr int kLrSf = (kLrDy * kLrDz + kLrThreads - 1) / kLrThreads;   // sig_hat values
+
+template <typename T, int SP>
+__global__ void __launch_bounds__(kLrThreads)
+k_lim_res(const Fine *fines, const LrTile *tiles, int ntiles, const int *active,
+          const double *scal, int src, int b0_idx, int write_d64, double *partials)
+{
+    __shared__ double Pl[4][kLrPy * kLrPz];
+    __shared__ double Dl[3][kLrDy * kLrDz];
+    __shared__ double red[kLrThreads / kWave];
+    const int tid = threadIdx.x;
+    // Workgroups are dealt to the 8 XCDs in turn, so virtual block v runs on
+    // XCD v % 8: tile (v % 8) * chunk + v / 8 gives each XCD a contiguous run
+    // of tiles, whose halos then meet in that XCD's L2.
+    const int chunk = (ntiles + 7) / 8;
+    for (int v = blockIdx.x; v < 8 * chunk; v += gridDim.x) {
+        const int t = (v & 7) * chunk + (v >> 3);
+        if (t >= ntiles)
+            continue;
+        const LrTile tl = tiles[t];
+        const Fine &f = fines[tl.prob];
+        const bool sp = layout_split<SP>(f.split);
+        if (active && !active[f.prob]) {
+            if (tid == 0)
+                partials[t] = 0.0;
+            continue;
+        }
+        const int nx = f.nx, ny = f.ny, nz = f.nz;
+        const long long sx = (long long)ny * nz, sy = nz;
+        const double *__restrict__ phi = f.phi[src];
+        const double *__restrict__ sig_hat = f.sig_hat;
+        const double *__restrict__ sa = f.sa64;
+        const double *__restrict__ jsrc = f.j;
+        T *__restrict__ b0 = (T *)f.b0[b0_idx];
+        float *__restrict__ D32 = (float *)f.D0;
+        double *__restrict__ D64 = f.D64;
+        const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
+        const double pb = f.phi_b;
+        const int i0 = tl.i0, i1 = tl.i0 + tl.ni, j0 = tl.j0, k0 = tl.k0;
+        // this thread's quad of the tile
+        const int jj = tid / (kLrTz / 4), kq = 4 * (tid - jj * (kLrTz / 4));
+        const int j = j0 + jj, kc = k0 + kq;
+        const bool own = j < ny && kc < nz;
+        double acc = 0.0;
+        double pf[kLrPf], sf[kLrSf];
+
+        // phi of plane pl (ghosts phi_b) into registers / their LDS slot
+        auto fetch_phi = [&](int pl) {
+            const bool in_x = pl >= 0 && pl < nx;
+#pragma unroll
+            for (int u = 0; u < kLrPf; ++u) {
+                const int e = tid + u * kLrThreads;
+                const int r = e / kLrPz, q = e - r * kLrPz;
+                const int jy = j0 - 2 + r, kz = k0 - 2 + q;
+                pf[u] = pb;
+                if (e < kLrPy * kLrPz && in_x && jy >= 0 && jy < ny && kz >= 0 && kz < nz)
+                    pf[u] = phi[(long long)pl * sx + (long long)jy * sy + kz];
+            }
+        };
+        auto commit_phi = [&](int pl) {
+            double *P = Pl[(pl + 4) & 3];
+#pragma unroll
+            for (int u = 0; u < kLrPf; ++u) {
+                const int e = tid + u * kLrThreads;
+                if (e < kLrPy * kLrPz)
+                    P[e] = pf[u];
+            }
+        };
+        // sig_hat of plane pl on the D region, into registers / the D slot
+        auto fetch_sig = [&](int pl) {
+            const bool in_x = pl >= 0 && pl < nx;
+#pragma unroll
+            for (int u = 0; u < kLrSf; ++u) {
+                const int e = tid + u * kLrThreads;
+                const int r = e / kLrDz, q = e - r * kLrDz;
+                const int jy = j0 - 1 + r, kz = k0 - 1 + q;
+                sf[u] = 1.0;
+                if (e < kLrDy * kLrDz && in_x && jy >= 0 && jy < ny && kz >= 0 && kz < nz)
+                    sf[u] = sig_hat[(long long)pl * sx + (long long)jy * sy + kz];
+            }
+        };
+        auto commit_sig = [&](int pl) {
+            double *Dd = Dl[(pl + 3) % 3];
+#pragma unroll
+            for (int u = 0; u < kLrSf; ++u) {
+                const int e = tid + u * kLrThreads;
+                if (e < kLrDy * kLrDz)
+                    Dd[e] = sf[u];
+            }
+        };
+        // prologue: phi(i0-2 .. i0) and sig_hat(i0-1)
+        fetch_phi(i0 - 2);
+        commit_phi(i0 - 2);
+        fetch_phi(i0 - 1);
+        commit_phi(i0 - 1);
+        fetch_phi(i0);
+        commit_phi(i0);
+        fetch_sig(i0 - 1);
+        commit_sig(i0 - 1);
+        __syncthreads();
+        for (int x = i0 - 2; x < i1; ++x) {
+            // the next step's loads, and this step's j and sa
+            const bool more = x + 1 < i1;
+            if (more) {
+                fetch_phi(x + 3);
+                fetch_sig(x + 2);
+            }
+            const bool res = x >= i0 && own;
+            const long long c0 = (long long)(res ? x : 0) * sx + (long long)j * sy + kc;
+            double jq[4], saq[4];
+            if (res) {
+                ld4(jsrc + c0, jq);
+                ld4(sa + c0, saq);
+            }
+            // D of plane x+1 on the tile and its halo (sig_hat waits in its slot)
+            const int pd = x + 1;
+            if (pd >= 0 && pd < nx && pd <= i1) {
+                const double *Pm = Pl[(pd + 3) & 3], *Pc = Pl[(pd + 4) & 3];
+                const double *Pp = Pl[(pd + 5) & 3];
+                double *Dd = Dl[(pd + 3) % 3];
+                for (int e = tid; e < kLrDy * kLrDz; e += kLrThreads) {
+                    const int r = e / kLrDz, q = e - r * kLrDz;
+                    const int jy = j0 - 1 + r, kz = k0 - 1 + q;
+                    if (jy < 0 || jy >= ny || kz < 0 || kz >= nz)
+                        continue;
+                    const int pc = (r + 1) * kLrPz + (q + 1);
+                    const double dx = Pp[pc] - Pm[pc], dy = Pc[pc + kLrPz] - Pc[pc - kLrPz];
+                    const double dz = Pc[pc + 1] - Pc[pc - 1];
+                    const double grad = sqrt(dx * dx + dy * dy + dz * dz) / (2.0 * f.h);
+                    const double sh = Dd[e];
+                    const double R = fmax(grad, floor_) / fmax(sh * Pc[pc], floor_);
+                    Dd[e] = limiter(f.limiter, R, f.larsen_n) / sh;
+                }
+            }
+            __syncthreads();
+            // residual of plane x
+            if (res) {
+                const double *Pm = Pl[(x + 3) & 3], *Pc = Pl[(x + 4) & 3];
+                const double *Pp = Pl[(x + 5) & 3];
+                const double *Dm = Dl[(x + 2) % 3], *Dc_ = Dl[(x + 3) % 3];
+                const double *Dp = Dl[(x + 4) % 3];
+                double rq[4], dq[4];
+                T bq[4];
+                float d32[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int k = kc + m;
+                    const int pc = (jj + 2) * kLrPz + (kq + m + 2);
+                    const int dc = (jj + 1) * kLrDz + (kq + m + 1);
+                    const double Dcv = Dc_[dc];
+                    const double gD = f.mirror ? Dcv : f.dghost;
+                    double F[6];
+                    F[0] = 0.5 * (Dcv + (x > 0 ? Dm[dc] : gD));
+                    F[1] = 0.5 * (Dcv + (x < nx - 1 ? Dp[dc] : gD));
+                    F[2] = 0.5 * (Dcv + (j > 0 ? Dc_[dc - kLrDz] : gD));
+                    F[3] = 0.5 * (Dcv + (j < ny - 1 ? Dc_[dc + kLrDz] : gD));
+                    F[4] = 0.5 * (Dcv + (k > 0 ? Dc_[dc - 1] : gD));
+                    F[5] = 0.5 * (Dcv + (k < nz - 1 ? Dc_[dc + 1] : gD));
+                    double num = jq[m] * f.h2;
+                    double den = saq[m] * f.h2;
+                    num = num + F[0] * Pm[pc]; den = den + F[0];
+                    num = num + F[1] * Pp[pc]; den = den + F[1];
+                    num = num + F[2] * Pc[pc - kLrPz]; den = den + F[2];
+                    num = num + F[3] * Pc[pc + kLrPz]; den = den + F[3];
+                    num = num + F[4] * Pc[pc - 1]; den = den + F[4];
+                    num = num + F[5] * Pc[pc + 1]; den = den + F[5];
+                    rq[m] = (num - Pc[pc] * den) / f.h2;
+                    bq[m] = (T)rq[m];
+                    acc += rq[m] * rq[m];
+                    dq[m] = Dcv;
+                    d32[m] = (float)Dcv;
+                }
+                const int q0 = (x + j) & 1;
+                if (sp)
+                    st4s(b0, c0, q0, bq);
+                else
+                    st4(b0 + c0, bq);
+                if (sizeof(T) == 4) {
+                    if (sp)
+                        st4s(D32, c0, q0, d32);
+                    else
+                        st4(D32 + c0, d32);
+                }
+                if (write_d64)
+                    st4(D64 + c0, dq);
+            }
+            __syncthreads();
+            // phi(x+3) into the slot of phi(x-1), sig_hat(x+2) into that of D(x-1)
+            if (more) {
+                commit_phi(x + 3);
+                commit_sig(x + 2);
+            }
+            __syncthreads();
+        }
+        // the tile's partial sum of r^2: wave shuffles, then the waves in order
+        for (int o = kWave / 2; o > 0; o >>= 1)
+            acc += __shfl_down(acc, o, kWave);
+        if ((tid & (kWave - 1)) == 0)
+            red[tid / kWave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kLrThreads / kWave; ++w)
+                s += red[w];
+            partials[t] = s;
+        }
+        __syncthreads();
+    }
+}
+
 // p_new = e + beta p_old (stored in precision T) and the partial sums of
 // r . p_new and p_new . A(D) p_new with the FP64 finest operator
 // (A x)_c = (x_c den - sum_s D_ps x_s)/h^2, zero ghosts.
@@ -2911,6 +3140,17 @@ void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int nt
 {
     hipLaunchKernelGGL(FLD_PICK(k_residual, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, src, use_tmp, b0_idx, r_out, partials);
+}
+
+void launch_lim_res(hipStream_t s, const Fine *fines, const LrTile *tiles, int ntiles,
+                    const int *active, const double *scal, int src, int b0_idx, int write_d64,
+                    double *partials, int mixed)
+{
+    if (ntiles > 0)
+        hipLaunchKernelGGL(FLD_PICK(k_lim_res, mixed), dim3(std::min(8 * ((ntiles + 7) / 8), 4096)),
+                           dim3(kLrThreads), 0,
+                           s, fines, tiles, ntiles, active, scal, src, b0_idx, write_d64,
+                           partials);
 }
 
 void launch_rel(hipStream_t s, int nprob, double *scal, const int *active)
