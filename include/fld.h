@@ -153,6 +153,12 @@ typedef struct fld_options {
                              and residual passes, which are faster with the LP limiter on
                              MI355X.  D and r are the same either way; only the grouping
                              of the partial sums of the residual norm differs               */
+    int fuse_rb;          /* multigrid: 1 runs the finest level's smoothing sweeps in pairs
+                             of single-pass red-black sweeps over LDS tiles, out of place
+                             into a second correction buffer (20 instead of 28 bytes per
+                             cell and sweep) when every grid has nz % 4 == 0; an odd
+                             sweep left over uses the two half-sweeps.  0 (default): the
+                             half-sweeps only.  The result is the same either way         */
 } fld_options;
 
 typedef struct fld_report {

@@ -33,6 +33,7 @@ struct Level {
     long long n = 0;
     double h = 0.0;
     void *e = nullptr, *b = nullptr, *sa = nullptr, *f = nullptr;
+    void *e2 = nullptr;    // finest level, fused sweeps only
     double *band = nullptr;
 };
 
@@ -94,6 +95,11 @@ struct fld_engine_impl {
     int *d_aa_range = nullptr;
     // fused limiter-residual pass: tiles of every problem, problem by problem
     bool fuse = false;
+    // single-pass red-black sweeps of the finest level: tiles of every
+    // problem (tile.prob: its level-0 grid)
+    bool fuse_rb = false;
+    LrTile *d_rbtiles = nullptr;
+    int n_rbtiles = 0;
     LrTile *d_lrtiles = nullptr;
     int n_lrtiles = 0;
     int *d_lr_range = nullptr;
@@ -556,6 +562,9 @@ struct fld_engine_impl {
     fld_status build_hierarchy()
     {
         std::vector<Grid> grids[2];
+        fuse_rb = opt.fuse_rb != 0;
+        for (int p = 0; p < nprob; ++p)
+            fuse_rb = fuse_rb && probs[p].fine.nz % 4 == 0;
         for (int p = 0; p < nprob; ++p) {
             Prob &P = probs[p];
             // levels: 2:1 on all axes while every axis is even and half of it >= 4
@@ -579,6 +588,8 @@ struct fld_engine_impl {
                     L.e = P.fine.e0;
                     L.b = P.fine.b0[0];
                     L.sa = P.fine.sa0;
+                    if (fuse_rb)
+                        CK(dalloc(&L.e2, tsz * L.n));
                 } else {
                     CK(dalloc(&L.e, tsz * L.n));
                     CK(dalloc(&L.b, tsz * L.n));
@@ -606,6 +617,7 @@ struct fld_engine_impl {
                 g.finer = l > 0 ? P.gid0 + l - 1 : -1;
                 g.coarser = l + 1 < P.nlev ? P.gid0 + l + 1 : -1;
                 g.e = L.e; g.b = L.b; g.sa = L.sa; g.D = l == 0 ? P.fine.D0 : nullptr; g.f = L.f;
+                g.e2 = L.e2;
                 g.band = L.band;
                 grids[0].push_back(g);
                 if (l == 0)
@@ -614,6 +626,21 @@ struct fld_engine_impl {
             }
         }
         ngrids = (int)grids[0].size();
+        if (fuse_rb) {
+            std::vector<LrTile> rt;
+            for (const Prob &P : probs) {
+                const Fine &f = P.fine;
+                for (int i0 = 0; i0 < f.nx; i0 += kLrTilePlanes)
+                    for (int j0 = 0; j0 < f.ny; j0 += kLrTileRows)
+                        for (int k0 = 0; k0 < f.nz; k0 += kLrTileCells)
+                            rt.push_back(LrTile{P.gid0, i0, std::min(kLrTilePlanes, f.nx - i0), j0,
+                                                k0});
+            }
+            n_rbtiles = (int)rt.size();
+            CK(dalloc(&d_rbtiles, sizeof(LrTile) * rt.size()));
+            HK(hipMemcpy(d_rbtiles, rt.data(), sizeof(LrTile) * rt.size(), hipMemcpyHostToDevice),
+               "hipMemcpy");
+        }
         for (int q = 0; q < 2; ++q) {
             CK(dalloc(&d_grids[q], sizeof(Grid) * ngrids));
             HK(hipMemcpy(d_grids[q], grids[q].data(), sizeof(Grid) * ngrids, hipMemcpyHostToDevice),
@@ -1019,6 +1046,16 @@ struct fld_engine_impl {
             toc(a, 0, (opt.omega_s != 1.0 ? 3.5 : 3.0) * sizeof(T));
     }
 
+    // One finest-level sweep in one pass (first colour, then the other), out
+    // of place (dir 0: e -> e2, 1: back): e, D, b and sa read, e written.
+    template <typename T>
+    void smooth_rb(Grid *G, int first, int dir)
+    {
+        hipEvent_t a = tic();
+        launch_smooth_rb<T>(stream, G, d_rbtiles, n_rbtiles, d_active, first, dir, opt.omega_s, lsp);
+        toc(a, 0, 5.0 * sizeof(T));
+    }
+
     double active_fine_cells() const
     {
         double c = 0.0;
@@ -1042,7 +1079,13 @@ struct fld_engine_impl {
                                      d_alpha, kmode);
                 else
                     launch_zero<T>(stream, G, mid[l].d, mid[l].n, d_active);
-                for (int s = 0; s < opt.nu1; ++s) {
+                int s = 0;
+                if (l == 0 && fuse_rb)
+                    for (; s + 1 < opt.nu1; s += 2) {
+                        smooth_rb<T>(G, 0, 0);
+                        smooth_rb<T>(G, 0, 1);
+                    }
+                for (; s < opt.nu1; ++s) {
                     smooth<T>(G, l, 0);
                     smooth<T>(G, l, 1);
                 }
@@ -1062,7 +1105,13 @@ struct fld_engine_impl {
                 continue;
             launch_prolong<T>(stream, G, mid[l].d, mid[l].n, d_active, lsp,
                               l == 0 ? opt.corr_scale : 1.0);
-            for (int s = 0; s < opt.nu2; ++s) {
+            int s = 0;
+            if (l == 0 && fuse_rb)
+                for (; s + 1 < opt.nu2; s += 2) {
+                    smooth_rb<T>(G, 1, 0);
+                    smooth_rb<T>(G, 1, 1);
+                }
+            for (; s < opt.nu2; ++s) {
                 smooth<T>(G, l, 1);
                 smooth<T>(G, l, 0);
             }
@@ -1448,6 +1497,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->nested_tol > 0.0 && o->anisotropy_g != 0.0) { err = "nested_tol needs anisotropy_g = 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->aa_m < 0 || o->aa_m > aa_max_window()) { err = "aa_m must lie in [0,16]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->fuse_lr != 0 && o->fuse_lr != 1) { err = "fuse_lr must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->fuse_rb != 0 && o->fuse_rb != 1) { err = "fuse_rb must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->aa_reg >= 0.0 && std::isfinite(o->aa_reg))) { err = "aa_reg must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
@@ -1562,6 +1612,7 @@ fld_status fld_default_options(fld_options *o)
     o->aa_m = 0;
     o->aa_reg = 1e-10;
     o->fuse_lr = 0;
+    o->fuse_rb = 0;
     return FLD_OK;
 }
 

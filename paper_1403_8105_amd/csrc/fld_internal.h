@@ -37,6 +37,7 @@ struct Grid {
     int split;       // e, b, sa, D stored colour by colour (see Fine::split)
     int pad;
     void *e, *b, *sa, *D, *f;
+    void *e2;        // finest level: second correction buffer of the fused sweep
     double *band;    // coarsest level: banded Cholesky factor of h^2 A, n*(ny*nz+1)
 };
 
@@ -238,6 +239,13 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
 // into Grid::band (the solve kernels and the tail then substitute only); it
 // reads only the coarse operators, so it may run on a second stream beside the
 // down-sweep.  fail[prob] is set to 1 when a pivot is not positive.
+// One red-black sweep of the finest level (first colour `first`, then the
+// other) in one pass over LrTile tiles (tile.prob: the level-0 grid index),
+// out of place: dir 0 reads Grid::e and writes Grid::e2, dir 1 the reverse.
+// The same result as the two half-sweeps of launch_smooth.  Needs nz % 4 == 0.
+template <typename T>
+void launch_smooth_rb(hipStream_t s, const Grid *grids, const LrTile *tiles, int ntiles,
+                      const int *active, int first, int dir, double omega, int sp);
 // Limiter and residual of the finest level in one pass over LrTile tiles
 // (grids with nz % 4 == 0): D (precision T; also FP64 when write_d64), r in
 // b0[b0_idx] (precision T) and one partial sum of r^2 per tile; the same D and

@@ -2164,6 +2164,206 @@ k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, in
     smooth_tasks<T, false>(grids, tasks, ntasks, active, colour, omega);
 }
 
+// One red-black sweep of the finest level in a single pass, out of place
+// (e -> e2 or back, dir): a block marches along x through a tile of kLrTy
+// rows by kLrTz cells along z, keeping four planes of e and of D (two-cell
+// halo) and two planes of b and sa (one-cell halo) in LDS.  Step x updates
+// the first colour of plane x+1 on the tile and its halo, then the second
+// colour of plane x on the tile, and stores plane x; the next planes' loads
+// are issued at the start of the step.  Reading the old field only (the new
+// one goes to the other buffer) makes a tile's halo independent of its
+// neighbours' progress, so the result is the red and black half-sweeps'
+// exactly: the same arithmetic per cell in the same order.  Each colour's new
+// value is formed by every tile whose halo holds it; 20 bytes per cell of the
+// grid move (e, D, b, sa read, e written) instead of 28 for two half-sweeps.
+constexpr int kRbPf = (kLrPy * kLrPz + kLrThreads - 1) / kLrThreads;   // e, D per thread
+constexpr int kRbBf = (kLrDy * kLrDz + kLrThreads - 1) / kLrThreads;   // b, sa per thread
+
+template <typename T, int SP>
+__global__ void __launch_bounds__(kLrThreads)
+k_smooth_rb(const Grid *grids, const LrTile *tiles, int ntiles, const int *active, int first,
+            int dir, T omega)
+{
+    __shared__ T El[4][kLrPy * kLrPz];
+    __shared__ T Dl[4][kLrPy * kLrPz];
+    __shared__ T Bl[2][kLrDy * kLrDz];
+    __shared__ T Sl[2][kLrDy * kLrDz];
+    const int tid = threadIdx.x;
+    const int chunk = (ntiles + 7) / 8;       // tiles per XCD, as in k_lim_res
+    for (int v = blockIdx.x; v < 8 * chunk; v += gridDim.x) {
+        const int t = (v & 7) * chunk + (v >> 3);
+        if (t >= ntiles)
+            continue;
+        const LrTile tl = tiles[t];
+        const Grid &g = grids[tl.prob];
+        if (active && !active[g.prob])
+            continue;
+        const bool sp = grid_split<SP>(g);
+        const int nx = g.nx, ny = g.ny, nz = g.nz;
+        const long long sx = (long long)ny * nz, sy = nz;
+        const T *__restrict__ ein = (const T *)(dir ? g.e2 : g.e);
+        T *__restrict__ eout = (T *)(dir ? g.e : g.e2);
+        const T *__restrict__ Dg = (const T *)g.D;
+        const T *__restrict__ bg = (const T *)g.b;
+        const T *__restrict__ sg = (const T *)g.sa;
+        const T h2 = (T)g.h2;
+        const T dgh = (T)g.dghost;
+        const int i0 = tl.i0, i1 = tl.i0 + tl.ni, j0 = tl.j0, k0 = tl.k0;
+        auto at = [&](long long c, int q) { return sp ? sidx(c, q) : c; };
+        T pe[kRbPf], pdv[kRbPf], pbv[kRbBf], psv[kRbBf];
+
+        // e and D of plane pl on the two-cell halo region (ghost e = 0)
+        auto fetch_ed = [&](int pl) {
+            const bool in_x = pl >= 0 && pl < nx;
+#pragma unroll
+            for (int u = 0; u < kRbPf; ++u) {
+                const int e = tid + u * kLrThreads;
+                const int r = e / kLrPz, q = e - r * kLrPz;
+                const int jy = j0 - 2 + r, kz = k0 - 2 + q;
+                pe[u] = (T)0;
+                pdv[u] = (T)0;
+                if (e < kLrPy * kLrPz && in_x && jy >= 0 && jy < ny && kz >= 0 && kz < nz) {
+                    const long long c = (long long)pl * sx + (long long)jy * sy + kz;
+                    const long long o = at(c, (pl + jy + kz) & 1);
+                    pe[u] = ein[o];
+                    pdv[u] = Dg[o];
+                }
+            }
+        };
+        auto commit_ed = [&](int pl) {
+            T *E = El[(pl + 4) & 3], *D = Dl[(pl + 4) & 3];
+#pragma unroll
+            for (int u = 0; u < kRbPf; ++u) {
+                const int e = tid + u * kLrThreads;
+                if (e < kLrPy * kLrPz) {
+                    E[e] = pe[u];
+                    D[e] = pdv[u];
+                }
+            }
+        };
+        // b and sa of plane pl on the one-cell halo region
+        auto fetch_bs = [&](int pl) {
+            const bool in_x = pl >= 0 && pl < nx;
+#pragma unroll
+            for (int u = 0; u < kRbBf; ++u) {
+                const int e = tid + u * kLrThreads;
+                const int r = e / kLrDz, q = e - r * kLrDz;
+                const int jy = j0 - 1 + r, kz = k0 - 1 + q;
+                pbv[u] = (T)0;
+                psv[u] = (T)0;
+                if (e < kLrDy * kLrDz && in_x && jy >= 0 && jy < ny && kz >= 0 && kz < nz) {
+                    const long long c = (long long)pl * sx + (long long)jy * sy + kz;
+                    const long long o = at(c, (pl + jy + kz) & 1);
+                    pbv[u] = bg[o];
+                    psv[u] = sg[o];
+                }
+            }
+        };
+        auto commit_bs = [&](int pl) {
+            T *B = Bl[(pl + 2) & 1], *S = Sl[(pl + 2) & 1];
+#pragma unroll
+            for (int u = 0; u < kRbBf; ++u) {
+                const int e = tid + u * kLrThreads;
+                if (e < kLrDy * kLrDz) {
+                    B[e] = pbv[u];
+                    S[e] = psv[u];
+                }
+            }
+        };
+        // new value of cell (pl, jy, kz) of the region: the point update of the
+        // half-sweep kernels, in their order (faces x-, x+, y-, y+, z-, z+)
+        auto update = [&](int pl, int r, int q, int jy, int kz) {
+            const T *Em = El[(pl + 3) & 3], *Ec = El[(pl + 4) & 3], *Ep = El[(pl + 5) & 3];
+            const T *Dm = Dl[(pl + 3) & 3], *Dc = Dl[(pl + 4) & 3], *Dp = Dl[(pl + 5) & 3];
+            const int pc = (r + 1) * kLrPz + (q + 1);          // in the e/D planes
+            const int bc = r * kLrDz + q;                      // in the b/sa planes
+            const T Dv = Dc[pc];
+            const T gD = g.mirror ? Dv : dgh;
+            T n_ = Bl[(pl + 2) & 1][bc] * h2;
+            T d_ = Sl[(pl + 2) & 1][bc] * h2;
+            T F;
+            F = (T)0.5 * (Dv + (pl > 0 ? Dm[pc] : gD));
+            n_ = n_ + F * (pl > 0 ? Em[pc] : (T)0); d_ = d_ + F;
+            F = (T)0.5 * (Dv + (pl < nx - 1 ? Dp[pc] : gD));
+            n_ = n_ + F * (pl < nx - 1 ? Ep[pc] : (T)0); d_ = d_ + F;
+            F = (T)0.5 * (Dv + (jy > 0 ? Dc[pc - kLrPz] : gD));
+            n_ = n_ + F * (jy > 0 ? Ec[pc - kLrPz] : (T)0); d_ = d_ + F;
+            F = (T)0.5 * (Dv + (jy < ny - 1 ? Dc[pc + kLrPz] : gD));
+            n_ = n_ + F * (jy < ny - 1 ? Ec[pc + kLrPz] : (T)0); d_ = d_ + F;
+            F = (T)0.5 * (Dv + (kz > 0 ? Dc[pc - 1] : gD));
+            n_ = n_ + F * (kz > 0 ? Ec[pc - 1] : (T)0); d_ = d_ + F;
+            F = (T)0.5 * (Dv + (kz < nz - 1 ? Dc[pc + 1] : gD));
+            n_ = n_ + F * (kz < nz - 1 ? Ec[pc + 1] : (T)0); d_ = d_ + F;
+            return omega * (n_ / d_) + ((T)1 - omega) * Ec[pc];
+        };
+
+        // prologue: e, D of planes i0-2 .. i0, b, sa of plane i0-1
+        fetch_ed(i0 - 2);
+        commit_ed(i0 - 2);
+        fetch_ed(i0 - 1);
+        commit_ed(i0 - 1);
+        fetch_ed(i0);
+        commit_ed(i0);
+        fetch_bs(i0 - 1);
+        commit_bs(i0 - 1);
+        __syncthreads();
+        const int c2 = first ^ 1;
+        for (int x = i0 - 2; x < i1; ++x) {
+            const bool more = x + 1 < i1;
+            if (more) {
+                fetch_ed(x + 3);
+                fetch_bs(x + 2);
+            }
+            // first colour on plane x+1, tile and halo
+            const int pu = x + 1;
+            if (pu >= 0 && pu < nx && pu <= i1) {
+                T *Eu = El[(pu + 4) & 3];
+                for (int e = tid; e < kLrDy * kLrDz; e += kLrThreads) {
+                    const int r = e / kLrDz, q = e - r * kLrDz;
+                    const int jy = j0 - 1 + r, kz = k0 - 1 + q;
+                    if (jy < 0 || jy >= ny || kz < 0 || kz >= nz || ((pu + jy + kz) & 1) != first)
+                        continue;
+                    const T nv = update(pu, r, q, jy, kz);
+                    Eu[(r + 1) * kLrPz + (q + 1)] = nv;
+                }
+            }
+            __syncthreads();
+            // second colour on plane x, the tile, then plane x stored
+            if (x >= i0) {
+                T *Ex = El[(x + 4) & 3];
+                const int jj = tid / (kLrTz / 4), kq = 4 * (tid - jj * (kLrTz / 4));
+                const int jy = j0 + jj, kc = k0 + kq;
+                if (jy < ny && kc < nz) {
+                    T nv[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int kz = kc + m;
+                        nv[m] = ((x + jy + kz) & 1) == c2 ? update(x, jj + 1, kq + m + 1, jy, kz)
+                                                           : (T)0;
+                    }
+                    T out[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const int pc = (jj + 2) * kLrPz + (kq + m + 2);
+                        out[m] = ((x + jy + kc + m) & 1) == c2 ? nv[m] : Ex[pc];
+                    }
+                    const long long c0 = (long long)x * sx + (long long)jy * sy + kc;
+                    if (sp)
+                        st4s(eout, c0, (x + jy) & 1, out);
+                    else
+                        st4(eout + c0, out);
+                }
+            }
+            __syncthreads();
+            if (more) {
+                commit_ed(x + 3);
+                commit_bs(x + 2);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Coarse right-hand side = 8-child mean of the fine residual b - A e.
 // Tasks run over the cells of the coarse grid.
 template <typename T, int SP>
@@ -3362,6 +3562,15 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
 }
 
 template <typename T>
+void launch_smooth_rb(hipStream_t s, const Grid *grids, const LrTile *tiles, int ntiles,
+                      const int *active, int first, int dir, double omega, int sp)
+{
+    if (ntiles > 0)
+        hipLaunchKernelGGL(FLD_PICK_SP(k_smooth_rb, T, sp), dim3(std::min(8 * ((ntiles + 7) / 8), 4096)),
+                           dim3(kLrThreads), 0, s, grids, tiles, ntiles, active, first, dir,
+                           (T)omega);
+}
+template <typename T>
 void launch_coarse_factor(hipStream_t s, const Grid *grids, const int *ids, int count,
                           const int *active, int *fail, int max_n)
 {
@@ -3414,7 +3623,9 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
     template void launch_tail<T>(hipStream_t, const Grid *, const int *, int, const int *, int *,  \
                                  int, int, double, int);                                         \
     template void launch_coarse_factor<T>(hipStream_t, const Grid *, const int *, int,           \
-                                          const int *, int *, int);
+                                          const int *, int *, int);                              \
+    template void launch_smooth_rb<T>(hipStream_t, const Grid *, const LrTile *, int,            \
+                                      const int *, int, int, double, int);
 
 FLD_INSTANTIATE(float)
 FLD_INSTANTIATE(double)

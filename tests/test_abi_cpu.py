@@ -52,6 +52,7 @@ def test_default_options():
     ({"nested_tol": 1e-3, "method": "rbsor"}, (8, 8, 8), 0.1),
     ({"nested_tol": 1e-3, "anisotropy_g": 0.5}, (8, 8, 8), 0.1),
     ({"fuse_lr": 2}, (8, 8, 8), 0.1),
+    ({"fuse_rb": -1}, (8, 8, 8), 0.1),
     ({"aa_m": 17}, (8, 8, 8), 0.1),
     ({"aa_reg": -1.0}, (8, 8, 8), 0.1),
 ])
