@@ -19,8 +19,8 @@ in device memory:
 3. Outer step (``anderson``): Anderson acceleration windows (``aa_m``) in
    place of the conjugate-gradient step for the winner, then a few schedules
    and correction factors with the best window (the best smoothing schedule
-   changes with the outer step).  Starting from the cached entry it runs
-   alone.
+   changes with the outer step), the regularisation, and how far the coarser
+   problem is solved first.  Starting from the cached entry it runs alone.
 
 The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
 limiter), in ``tuned.json`` beside this file unless another path is given.
@@ -53,6 +53,7 @@ AA_WINDOWS = [6, 8, 10, 12, 16]
 AA_REGS = [1e-8, 1e-6]          # tried after the default 1e-10 for the best window
 AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.0)]
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
+AA_NESTED = [3e-3, 1e-2, 3e-2, 1e-1]   # grid sequencing with the chosen window
 
 
 def cache_key(arch: str, shape, precision: str, limiter: str, tol: float | None = None) -> str:
@@ -225,6 +226,14 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                 best = better(run(b3["nu1"], b3["nu2"], b3["omega_s"], b3["restart_growth"],
                                   b3["corr_scale"], b3.get("nested_tol", 0.0), b3["aa_m"], reg),
                               best)
+            # how far to solve the coarser problem first, with the window chosen
+            b4 = best
+            if even:
+                for nt in AA_NESTED:
+                    if nt != b4.get("nested_tol", 0.0):
+                        best = better(run(b4["nu1"], b4["nu2"], b4["omega_s"],
+                                          b4["restart_growth"], b4["corr_scale"], nt, b4["aa_m"],
+                                          b4.get("aa_reg", 1e-10)), best)
     if best is None:
         raise RuntimeError("autotune: no candidate reached the tolerance")
     opts = {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"], "nu2": best["nu2"],
@@ -346,6 +355,12 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
             for reg in AA_REGS:
                 best = better(run(b3["nu1"], b3["nu2"], b3["omega_s"], b3["restart_growth"],
                                   b3["corr_scale"], b3["nested_tol"], b3["aa_m"], reg), best)
+            b4 = best
+            for nt in AA_NESTED:
+                if nt != b4["nested_tol"]:
+                    best = better(run(b4["nu1"], b4["nu2"], b4["omega_s"], b4["restart_growth"],
+                                      b4["corr_scale"], nt, b4["aa_m"], b4.get("aa_reg", 1e-10)),
+                                  best)
     keys = ("nu1", "nu2", "omega_s", "restart_growth", "corr_scale") + \
         (("nested_tol",) if best["nested_tol"] else ()) + (("aa_m",) if best.get("aa_m") else ()) + \
         (("aa_reg",) if best.get("aa_m") and best.get("aa_reg", 1e-10) != 1e-10 else ())
