@@ -51,7 +51,8 @@ NESTED = [1e-3, 1e-2]
 DEFAULT_SCHEDULE = (2, 2, 1.0, 2.0)
 AA_WINDOWS = [6, 8, 10, 12, 16]
 AA_REGS = [1e-8, 1e-6]          # tried after the default 1e-10 for the best window
-AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.0)]
+AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.0), (5, 5, 1.15),
+                (6, 6, 1.15), (4, 4, 1.25)]
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 AA_NESTED = [3e-3, 1e-2, 3e-2, 1e-1]   # grid sequencing with the chosen window
 
