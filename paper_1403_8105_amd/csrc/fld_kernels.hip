@@ -2505,41 +2505,123 @@ k_galerkin(const Grid *grids, const Task *tasks, int ntasks, const int *active)
         // tasks run over the padded face grid; padding entries get zeros
         const long long nf = (long long)(C.nx + 1) * (C.ny + 1) * face_zstride(C.nz);
         const Dec dec(C.ny + 1, (int)face_zstride(C.nz));
+        auto one = [&](long long c, int I, int J, int K) {
+                // x faces
+                T v = (T)0;
+                if (J < C.ny && K < C.nz) {
+                    T s = (T)0;
+                    s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K, sp);
+                    s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K + 1, sp);
+                    s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K, sp);
+                    s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K + 1, sp);
+                    v = (T)0.5 * s;
+                }
+                fc[c] = v;
+                v = (T)0;
+                if (I < C.nx && K < C.nz) {
+                    T s = (T)0;
+                    s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K, sp);
+                    s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K + 1, sp);
+                    s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K, sp);
+                    s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K + 1, sp);
+                    v = (T)0.5 * s;
+                }
+                fc[nf + c] = v;
+                v = (T)0;
+                if (I < C.nx && J < C.ny && K <= C.nz) {
+                    T s = (T)0;
+                    s = s + face_below<T>(F, 2, 2 * I, 2 * J, 2 * K, sp);
+                    s = s + face_below<T>(F, 2, 2 * I, 2 * J + 1, 2 * K, sp);
+                    s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J, 2 * K, sp);
+                    s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J + 1, 2 * K, sp);
+                    v = (T)0.5 * s;
+                }
+                fc[2 * nf + c] = v;
+        };
+        if (F.fine && (F.nz & 3) == 0 && (tk.start & 1) == 0 && (tk.count & 1) == 0) {
+            // finest level below: two coarse cells along z per thread, whose
+            // fine faces come from quads of D (z rows 2K..2K+3) and the cell
+            // before them; per face the arithmetic and the order of the sums
+            // are face_below's and the loop's above
+            const T *__restrict__ D = (const T *)F.D;
+            const T gdh = (T)F.dghost;
+            const bool mir = F.mirror != 0;
+            auto quad = [&](int i, int j, int k0, T v[4]) {
+                const long long x = ((long long)i * F.ny + j) * F.nz + k0;
+                if (sp)
+                    ld4s(D, x, (i + j) & 1, v);
+                else
+                    ld4(D + x, v);
+            };
+            auto face = [&](T hi, T lo, bool lo_in) {
+                return lo_in ? (T)0.5 * (hi + lo) : (T)0.5 * (hi + (mir ? hi : gdh));
+            };
+            for (int q = threadIdx.x; q < (tk.count >> 1); q += blockDim.x) {
+                const long long c = tk.start + 2 * (long long)q;
+                int I, J, K;
+                dec(c, I, J, K);
+                if (!(I < C.nx && J < C.ny && K + 1 < C.nz)) {
+                    one(c, I, J, K);
+                    one(c + 1, I, J, K + 1);
+                    continue;
+                }
+                const int i = 2 * I, j = 2 * J, k0 = 2 * K;
+                // rows (i+di, j+dj), z k0..k0+3, and the cell at k0-1
+                T r00[4], r01[4], r10[4], r11[4], xm0[4], xm1[4], ym0[4], ym1[4];
+                quad(i, j, k0, r00);
+                quad(i, j + 1, k0, r01);
+                quad(i + 1, j, k0, r10);
+                quad(i + 1, j + 1, k0, r11);
+                const bool xin = i > 0, yin = j > 0, zin = k0 > 0;
+                if (xin) {
+                    quad(i - 1, j, k0, xm0);
+                    quad(i - 1, j + 1, k0, xm1);
+                }
+                if (yin) {
+                    quad(i, j - 1, k0, ym0);
+                    quad(i + 1, j - 1, k0, ym1);
+                }
+                T z00 = (T)0, z01 = (T)0, z10 = (T)0, z11 = (T)0;
+                if (zin) {
+                    z00 = D[cell_at(F, i, j, k0 - 1, sp)];
+                    z01 = D[cell_at(F, i, j + 1, k0 - 1, sp)];
+                    z10 = D[cell_at(F, i + 1, j, k0 - 1, sp)];
+                    z11 = D[cell_at(F, i + 1, j + 1, k0 - 1, sp)];
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {       // coarse cells K and K+1
+                    const int a = 2 * h;            // fine z offset within the quad
+                    T s = (T)0;
+                    // x faces below (i, j+dj, k0+a+dk): lower cell (i-1, ...)
+                    s = s + face(r00[a], xin ? xm0[a] : (T)0, xin);
+                    s = s + face(r00[a + 1], xin ? xm0[a + 1] : (T)0, xin);
+                    s = s + face(r01[a], xin ? xm1[a] : (T)0, xin);
+                    s = s + face(r01[a + 1], xin ? xm1[a + 1] : (T)0, xin);
+                    fc[c + h] = (T)0.5 * s;
+                    // y faces below (i+di, j, k0+a+dk): lower cell (i+di, j-1, ...)
+                    s = (T)0;
+                    s = s + face(r00[a], yin ? ym0[a] : (T)0, yin);
+                    s = s + face(r00[a + 1], yin ? ym0[a + 1] : (T)0, yin);
+                    s = s + face(r10[a], yin ? ym1[a] : (T)0, yin);
+                    s = s + face(r10[a + 1], yin ? ym1[a + 1] : (T)0, yin);
+                    fc[nf + c + h] = (T)0.5 * s;
+                    // z faces below (i+di, j+dj, k0+a): lower cell at k0+a-1
+                    const bool zl = h == 1 || zin;
+                    s = (T)0;
+                    s = s + face(r00[a], h ? r00[1] : z00, zl);
+                    s = s + face(r01[a], h ? r01[1] : z01, zl);
+                    s = s + face(r10[a], h ? r10[1] : z10, zl);
+                    s = s + face(r11[a], h ? r11[1] : z11, zl);
+                    fc[2 * nf + c + h] = (T)0.5 * s;
+                }
+            }
+            continue;
+        }
         for (int q = threadIdx.x; q < tk.count; q += blockDim.x) {
             const long long c = tk.start + q;
             int I, J, K;
             dec(c, I, J, K);
-            // x faces
-            T v = (T)0;
-            if (J < C.ny && K < C.nz) {
-                T s = (T)0;
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K, sp);
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J, 2 * K + 1, sp);
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K, sp);
-                s = s + face_below<T>(F, 0, 2 * I, 2 * J + 1, 2 * K + 1, sp);
-                v = (T)0.5 * s;
-            }
-            fc[c] = v;
-            v = (T)0;
-            if (I < C.nx && K < C.nz) {
-                T s = (T)0;
-                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K, sp);
-                s = s + face_below<T>(F, 1, 2 * I, 2 * J, 2 * K + 1, sp);
-                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K, sp);
-                s = s + face_below<T>(F, 1, 2 * I + 1, 2 * J, 2 * K + 1, sp);
-                v = (T)0.5 * s;
-            }
-            fc[nf + c] = v;
-            v = (T)0;
-            if (I < C.nx && J < C.ny && K <= C.nz) {
-                T s = (T)0;
-                s = s + face_below<T>(F, 2, 2 * I, 2 * J, 2 * K, sp);
-                s = s + face_below<T>(F, 2, 2 * I, 2 * J + 1, 2 * K, sp);
-                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J, 2 * K, sp);
-                s = s + face_below<T>(F, 2, 2 * I + 1, 2 * J + 1, 2 * K, sp);
-                v = (T)0.5 * s;
-            }
-            fc[2 * nf + c] = v;
+            one(c, I, J, K);
         }
     }
 }
