@@ -380,6 +380,15 @@ def main():
                      "avg_launch_us": avg_s * 1e6},
         "kernels": kernels,
     }
+    # the half-sweep's working set (4 arrays of 4 or 8 B per cell) against the
+    # 256 MB Infinity Cache of MI355X: when it fits, part of the traffic is
+    # served from there and frac is not a clean HBM fraction
+    work_set = 4 * (4 if args.precision == "mixed" else 8) * n ** 3
+    line["roofline"]["note"] = (
+        f"working set {work_set / 2**20:.0f} MiB "
+        + ("fits the 256 MiB Infinity Cache: cache-assisted, not a clean HBM fraction "
+           "(the 512^3 workload gives that)" if work_set <= 256 * 2**20 else
+           "exceeds the 256 MiB Infinity Cache: an HBM fraction"))
     if not args.no_fp64:
         log("bench: plain FP64 GPU solve of the same medium")
         s64 = make("fp64", 0)

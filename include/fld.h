@@ -159,6 +159,10 @@ typedef struct fld_options {
                              cell and sweep) when every grid has nz % 4 == 0; an odd
                              sweep left over uses the two half-sweeps.  0 (default): the
                              half-sweeps only.  The result is the same either way         */
+    int debug_nan_iter;   /* failure injection (multigrid): k >= 1 writes NaN into voxel 0 of
+                             every problem's phi after the residual of outer iteration k
+                             is read, so the next residual is not finite and the solve
+                             ends with FLD_ERR_DIVERGED at iteration k+1; 0 (default) off  */
 } fld_options;
 
 typedef struct fld_report {

@@ -40,7 +40,8 @@ import sys
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-CACHE = os.path.join(HERE, "tuned.json")
+# FLD_TUNE_CACHE names another cache file (read by tuned_options, written by tune)
+CACHE = os.environ.get("FLD_TUNE_CACHE") or os.path.join(HERE, "tuned.json")
 
 SHAPES = [(4096, 2048), (2048, 2048), (8192, 2048), (16384, 2048), (4096, 1024), (4096, 4096)]
 SCHEDULES = [(2, 2, 1.0), (1, 1, 1.0), (2, 1, 1.0), (1, 2, 1.0), (3, 3, 1.0), (2, 2, 1.15),

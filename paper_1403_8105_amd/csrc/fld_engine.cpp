@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -72,6 +73,12 @@ struct fld_engine_impl {
     std::vector<Prob> probs;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // FLD_LOG set (and not "0"): one JSON line per problem and outer
+    // iteration on stderr
+    const bool log_iters = [] {
+        const char *v = std::getenv("FLD_LOG");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
     std::vector<void *> allocs;
     std::string err;
 
@@ -1320,6 +1327,9 @@ struct fld_engine_impl {
                 const double rel = sc[(size_t)p * S_COUNT + S_REL];
                 P.hist.push_back(rel);
                 P.final_k = k;
+                if (log_iters)
+                    std::fprintf(stderr, "{\"fld_iteration\": %d, \"problem\": %d, \"rel\": %.17g}\n",
+                                 k, p, rel);
                 if (!std::isfinite(rel)) {
                     P.status = FLD_ERR_DIVERGED;
                     h_active[p] = 0;
@@ -1336,6 +1346,8 @@ struct fld_engine_impl {
             if (!n_active)
                 break;
             CK(sync_active());
+            if (opt.debug_nan_iter > 0 && k == opt.debug_nan_iter)
+                launch_poison(stream, d_fines, N, k & 1);
             for (int p = 0; p < N; ++p)
                 if (h_active[p])
                     for (int l = 0; l + 1 < probs[p].nlev; ++l)
@@ -1498,6 +1510,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->aa_m < 0 || o->aa_m > aa_max_window()) { err = "aa_m must lie in [0,16]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->fuse_lr != 0 && o->fuse_lr != 1) { err = "fuse_lr must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->fuse_rb != 0 && o->fuse_rb != 1) { err = "fuse_rb must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->debug_nan_iter < 0) { err = "debug_nan_iter must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->aa_reg >= 0.0 && std::isfinite(o->aa_reg))) { err = "aa_reg must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
@@ -1613,6 +1626,7 @@ fld_status fld_default_options(fld_options *o)
     o->aa_reg = 1e-10;
     o->fuse_lr = 0;
     o->fuse_rb = 0;
+    o->debug_nan_iter = 0;
     return FLD_OK;
 }
 

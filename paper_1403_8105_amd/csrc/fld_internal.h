@@ -239,6 +239,8 @@ void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int c
 // into Grid::band (the solve kernels and the tail then substitute only); it
 // reads only the coarse operators, so it may run on a second stream beside the
 // down-sweep.  fail[prob] is set to 1 when a pivot is not positive.
+// Failure injection: phi[src][0] = NaN for each of the nprob problems.
+void launch_poison(hipStream_t s, const Fine *fines, int nprob, int src);
 // One red-black sweep of the finest level (first colour `first`, then the
 // other) in one pass over LrTile tiles (tile.prob: the level-0 grid index),
 // out of place: dir 0 reads Grid::e and writes Grid::e2, dir 1 the reverse.

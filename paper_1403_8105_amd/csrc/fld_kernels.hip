@@ -3435,6 +3435,18 @@ void launch_lim_res(hipStream_t s, const Fine *fines, const LrTile *tiles, int n
                            partials);
 }
 
+__global__ void k_poison(const Fine *fines, int nprob, int src)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob)
+        fines[p].phi[src][0] = __builtin_nan("");
+}
+
+void launch_poison(hipStream_t s, const Fine *fines, int nprob, int src)
+{
+    hipLaunchKernelGGL(k_poison, dim3((nprob + 63) / 64), dim3(64), 0, s, fines, nprob, src);
+}
+
 void launch_rel(hipStream_t s, int nprob, double *scal, const int *active)
 {
     hipLaunchKernelGGL(k_rel, dim3((nprob + 63) / 64), dim3(64), 0, s, nprob, scal, active);
