@@ -126,8 +126,9 @@ struct fld_engine_impl {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     long long tail_lds = 0;
     int max_coarse_n = 1, max_coarse_bw = 1;
-    // kernel instance choice: kmode 0 FP64, 1 FP32 natural, 2 FP32 colour-split,
-    // 3 FP32 per problem; lsp the same for the level kernels (0 / 1 / 2)
+    // kernel instance choice: kmode 0 FP64 natural, 1 FP32 natural, 2 FP32
+    // colour-split, 3 FP32 per problem, 4 FP64 colour-split, 5 FP64 per
+    // problem; lsp the layout alone for the level kernels (0 / 1 / 2)
     int kmode = 0, lsp = 0;
     int max_levels = 0;
     double *d_part[4] = {};
@@ -454,11 +455,13 @@ struct fld_engine_impl {
             f.limiter = opt.limiter;
             f.write_sighat = P.chan == 0;
             f.sig_hat = V.sig_hat;
-            // colour-split FP32 fields: the split smoother needs 8-cell z runs,
-            // and the finest level must be smoothed (not the coarsest)
+            // colour-split fields of the V-cycle's finest level (e, b, D and
+            // sigma_a in the V-cycle's precision): the split smoother needs
+            // 8-cell z runs, and the finest level must be smoothed (not the
+            // coarsest)
             const bool coarsens = V.nx % 2 == 0 && V.ny % 2 == 0 && V.nz % 2 == 0 &&
                                   V.nx / 2 >= 4 && V.ny / 2 >= 4 && V.nz / 2 >= 4;
-            f.split = mixed && mg && opt.colour_split && V.nz % 8 == 0 && coarsens;
+            f.split = mg && opt.colour_split && V.nz % 8 == 0 && coarsens;
             const size_t N8 = sizeof(double) * V.n, NT = tsz * V.n;
             // split fields hold whole 64-cell blocks
             const size_t NS = f.split ? tsz * (size_t)((V.n + 63) / 64 * 64) : NT;
@@ -475,7 +478,8 @@ struct fld_engine_impl {
                 CK(dalloc(&f.e0, NS));
                 CK(dalloc(&f.p[0], NT));
                 CK(dalloc(&f.p[1], NT));
-                if (mixed) {
+                if (mixed || f.split) {
+                    // the smoother's D and sigma_a: FP32, or FP64 colour-split
                     CK(dalloc(&f.D0, NS));
                     CK(dalloc(&f.sa0, NS));
                 } else {
@@ -507,7 +511,7 @@ struct fld_engine_impl {
             for (const Prob &P : probs)
                 ns += P.fine.split ? 1 : 0;
             lsp = ns == 0 ? 0 : ns == nprob ? 1 : 2;
-            kmode = !mixed ? 0 : lsp + 1;
+            kmode = !mixed ? (lsp == 0 ? 0 : lsp + 3) : lsp + 1;
         }
         CK(upload_list(ft, fine_tasks));
         fuse = mg && opt.fuse_lr != 0;
@@ -1175,7 +1179,7 @@ struct fld_engine_impl {
             const bool d64 = !mixed || opt.aa_m == 0;
             launch_lim_res(stream, d_fines, d_lrtiles, n_lrtiles, d_active, d_scal, k & 1, k & 1,
                            d64 ? 1 : 0, d_lrpart, kmode);
-            toc(ta, 1, 32.0 + tsz + (mixed ? 4.0 : 0.0) + (d64 ? 8.0 : 0.0));
+            toc(ta, 1, 32.0 + tsz + (mixed ? 4.0 : lsp != 0 ? 8.0 : 0.0) + (d64 ? 8.0 : 0.0));
             launch_sum_partials(stream, N, d_lr_range, d_lrpart, d_scal, S_RES2, d_active);
             launch_rel(stream, N, d_scal, d_active);
             return;
@@ -1186,9 +1190,10 @@ struct fld_engine_impl {
         else
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
                            (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, kmode);
-        // limiter: phi and sig_hat read, D written (FP64, plus the FP32 copy in
-        // the mixed form); with the direction update also p read, phi written
-        toc(ta, 2, 24.0 + (mixed ? 4.0 : 0.0) + (first ? 0.0 : tsz + 8.0));
+        // limiter: phi and sig_hat read, D written (FP64, plus the smoother's
+        // copy: FP32 in the mixed form, colour-split FP64 in the FP64 form);
+        // with the direction update also p read, phi written
+        toc(ta, 2, 24.0 + (mixed ? 4.0 : lsp != 0 ? 8.0 : 0.0) + (first ? 0.0 : tsz + 8.0));
         ta = tic();
         launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, k & 1, 0, k & 1,
                         nullptr, d_part[0], kmode);

@@ -266,7 +266,8 @@ __device__ inline double limiter(int kind, double R, double n)
 
 __global__ void __launch_bounds__(kBlock)
 k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const double *albedo,
-        const double *Q, double sigma_eps, double aniso_g, double *partials, float *sa32)
+        const double *Q, double sigma_eps, double aniso_g, double *partials, float *sa32,
+        double *sa64s)
 {
     for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
         const Task tk = tasks[t];
@@ -280,14 +281,17 @@ k_setup(Fine f, const Task *tasks, int ntasks, const double *sigma_t, const doub
                 f.sig_hat[c] = fmax(sigma_t[c] * (1.0 - albedo[c] * aniso_g), sigma_eps);
             const double sa = (1.0 - albedo[c]) * fmax(sigma_t[c], sigma_eps);
             f.sa64[c] = sa;
-            if (sa32) {
+            if (sa32 || sa64s) {
                 long long o = c;
                 if (f.split) {
                     int i, j, k;
                     dec(c, i, j, k);
                     o = sidx(c, (i + j + k) & 1);
                 }
-                sa32[o] = (float)sa;
+                if (sa32)
+                    sa32[o] = (float)sa;
+                else
+                    sa64s[o] = sa;
             }
             const double jq = Q[c];
             f.j[c] = jq;
@@ -347,7 +351,10 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
         const T *__restrict__ dir = (const T *)f.p[dir_idx];
         const double *__restrict__ sig_hat = f.sig_hat;
         double *__restrict__ phi_out = f.phi[dst];
-        float *__restrict__ D32 = (float *)f.D0;
+        // the smoother's copy of D: FP32 in the mixed form; in the FP64 form
+        // a colour-split copy, or D64 itself when the level keeps natural order
+        T *__restrict__ Dlo = (T *)f.D0;
+        const bool put_lo = !to_tmp && (sizeof(T) == 4 || sp);
         const double theta = use_dir ? scal[f.prob * S_COUNT + S_THETA] : 0.0;
         const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
         const long long sx = (long long)f.ny * f.nz, sy = f.nz;
@@ -376,7 +383,7 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
                 Hood<double> P;
                 gather(P, L4, L1, c0, i, j, k0, f.nx, f.ny, f.nz, sx, sy, f.phi_b);
                 double sh[4], Rq[4], Dq[4];
-                float D32q[4];
+                T Dlq[4];
                 ld4(sig_hat + c0, sh);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
@@ -392,14 +399,14 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
 #pragma unroll 1
                 for (int m = 0; m < 4; ++m) {
                     Dq[m] = limiter(f.limiter, Rq[m], f.larsen_n) / sh[m];
-                    D32q[m] = (float)Dq[m];
+                    Dlq[m] = (T)Dq[m];
                 }
                 st4(Dout + c0, Dq);
-                if (!to_tmp && sizeof(T) == 4) {
+                if (put_lo) {
                     if (sp)
-                        st4s(D32, c0, (i + j) & 1, D32q);
+                        st4s(Dlo, c0, (i + j) & 1, Dlq);
                     else
-                        st4(D32 + c0, D32q);
+                        st4(Dlo + c0, Dlq);
                 }
             }
             continue;
@@ -428,8 +435,8 @@ k_limiter(const Fine *fines, const Task *tasks, int ntasks, const int *active, c
             const double R = fmax(grad, floor_) / fmax(sh * pc, floor_);
             const double D = limiter(f.limiter, R, f.larsen_n) / sh;
             Dout[c] = D;
-            if (!to_tmp && sizeof(T) == 4)
-                D32[sp ? sidx(c, (i + j + k) & 1) : c] = (float)D;
+            if (put_lo)
+                Dlo[sp ? sidx(c, (i + j + k) & 1) : c] = (T)D;
             if (use_dir && dst != src)
                 phi_out[c] = pc;
         }
@@ -656,7 +663,8 @@ k_lim_res(const Fine *fines, const LrTile *tiles, int ntiles, const int *active,
         const double *__restrict__ sa = f.sa64;
         const double *__restrict__ jsrc = f.j;
         T *__restrict__ b0 = (T *)f.b0[b0_idx];
-        float *__restrict__ D32 = (float *)f.D0;
+        T *__restrict__ Dlo = (T *)f.D0;       // as in k_limiter
+        const bool put_lo = sizeof(T) == 4 || sp;
         double *__restrict__ D64 = f.D64;
         const double floor_ = f.eps * scal[f.prob * S_COUNT + S_JBAR];
         const double pb = f.phi_b;
@@ -764,8 +772,7 @@ k_lim_res(const Fine *fines, const LrTile *tiles, int ntiles, const int *active,
                 const double *Dm = Dl[(x + 2) % 3], *Dc_ = Dl[(x + 3) % 3];
                 const double *Dp = Dl[(x + 4) % 3];
                 double rq[4], dq[4];
-                T bq[4];
-                float d32[4];
+                T bq[4], dlo[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int k = kc + m;
@@ -792,18 +799,18 @@ k_lim_res(const Fine *fines, const LrTile *tiles, int ntiles, const int *active,
                     bq[m] = (T)rq[m];
                     acc += rq[m] * rq[m];
                     dq[m] = Dcv;
-                    d32[m] = (float)Dcv;
+                    dlo[m] = (T)Dcv;
                 }
                 const int q0 = (x + j) & 1;
                 if (sp)
                     st4s(b0, c0, q0, bq);
                 else
                     st4(b0 + c0, bq);
-                if (sizeof(T) == 4) {
+                if (put_lo) {
                     if (sp)
-                        st4s(D32, c0, q0, d32);
+                        st4s(Dlo, c0, q0, dlo);
                     else
-                        st4(D32 + c0, d32);
+                        st4(Dlo + c0, dlo);
                 }
                 if (write_d64)
                     st4(D64 + c0, dq);
@@ -3360,21 +3367,33 @@ inline int grid_for(int ntasks)
     return ntasks < cap ? (ntasks > 0 ? ntasks : 1) : cap;
 }
 
+// One block per task, for stencil passes over the finest level: blocks are
+// dispatched in task order, so the tasks resident at any moment form one
+// contiguous run of planes and a plane's x-neighbours are read while it is
+// still in L2.  (With blocks striding over tasks, the blocks drift apart
+// and at 512^3 most x-neighbour planes are fetched from memory again.)
+inline int grid_per_task(int ntasks)
+{
+    return ntasks > 0 ? ntasks : 1;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
-// Kernel instance for a precision/layout mode: 0 FP64, 1 FP32 natural,
-// 2 FP32 colour-split, 3 FP32 decided per problem (instances share one
-// signature).
+// Kernel instance for a precision/layout mode: 0 FP64 natural, 1 FP32
+// natural, 2 FP32 colour-split, 3 FP32 decided per problem, 4 FP64
+// colour-split, 5 FP64 decided per problem (instances share one signature).
 #define FLD_PICK(K, mode)                                                      \
     ((mode) == 0 ? K<double, 0>                                                \
-                 : (mode) == 1 ? K<float, 0> : (mode) == 2 ? K<float, 1> : K<float, 2>)
+     : (mode) == 1 ? K<float, 0>                                               \
+     : (mode) == 2 ? K<float, 1>                                               \
+     : (mode) == 3 ? K<float, 2> : (mode) == 4 ? K<double, 1> : K<double, 2>)
 // Level kernels: the precision is the template's, sp is 0/1/2 as above.
 #define FLD_PICK_SP(K, T, sp)                                                  \
-    (sizeof(T) == 8 || (sp) == 0 ? K<T, 0> : (sp) == 1 ? K<T, 1> : K<T, 2>)
+    ((sp) == 0 ? K<T, 0> : (sp) == 1 ? K<T, 1> : K<T, 2>)
 
 void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
                   const double *sigma_t, const double *albedo, const double *Q,
@@ -3382,7 +3401,8 @@ void launch_setup(hipStream_t s, const Fine &f, const Task *tasks, int ntasks,
 {
     hipLaunchKernelGGL(k_setup, dim3(grid_for(ntasks)), dim3(kBlock), 0, s, f, tasks, ntasks,
                        sigma_t, albedo, Q, sigma_eps, aniso_g, partials,
-                       mixed ? (float *)f.sa0 : (float *)nullptr);
+                       mixed ? (float *)f.sa0 : (float *)nullptr,
+                       !mixed && f.split ? (double *)f.sa0 : (double *)nullptr);
 }
 
 void launch_sum_partials(hipStream_t s, int nprob, const int *range, const double *partials,
@@ -3420,7 +3440,7 @@ void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int nt
                      const int *active, int src, int use_tmp, int b0_idx, double *r_out,
                      double *partials, int mixed)
 {
-    hipLaunchKernelGGL(FLD_PICK(k_residual, mixed), dim3(grid_for(ntasks)), dim3(kBlock), 0, s, fines,
+    hipLaunchKernelGGL(FLD_PICK(k_residual, mixed), dim3(grid_per_task(ntasks)), dim3(kBlock), 0, s, fines,
                            tasks, ntasks, active, src, use_tmp, b0_idx, r_out, partials);
 }
 

@@ -92,6 +92,16 @@ def test_anderson_launch_variants_are_bit_identical():
     np.testing.assert_array_equal(part, full)
 
 
+def test_anderson_fp64_colour_split_is_bit_identical():
+    # the FP64 form's colour-split finest fields under Anderson acceleration,
+    # deflation and graph replay
+    st, al, Q, h = media.config("cloud256", n=32)
+    outs = [solve_gpu(st, al, Q, h, precision="fp64", tol=0.0, max_iters=9, aa_m=4,
+                      colour_split=split) for split in (0, 1)]
+    np.testing.assert_array_equal(outs[1][0], outs[0][0])
+    np.testing.assert_array_equal(outs[1][1]["history"], outs[0][1]["history"])
+
+
 def test_anderson_batch_equals_single_solves():
     vols = media.batch_config(nvol=3, size_scale=0.25, seed=3)
     dims = [(v["n"],) * 3 for v in vols]

@@ -254,15 +254,17 @@ def test_graph_replay_is_bit_identical():
     assert rep["kernel_bytes"][0] == rep["kernel_launches"][0] * 12.0 * st.size
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("shape,omega_s", [((32, 32, 32), 1.0), ((24, 16, 40), 1.0),
                                            ((16, 16, 8), 1.0), ((32, 24, 16), 1.2)])
-def test_colour_split_is_bit_identical(shape, omega_s):
-    # the red/black storage of the finest FP32 fields changes where values
-    # live, not how they are computed
+def test_colour_split_is_bit_identical(shape, omega_s, precision):
+    # the red/black storage of the V-cycle's finest fields (FP32 in the mixed
+    # form, FP64 in the FP64 form) changes where values live, not how they
+    # are computed
     st, al, Q, h = ragged_cloud(shape, seed=7)
     outs = []
     for split in (0, 1):
-        s = gpu_solver(shape, h, st, al, Q, precision="mixed", tol=0.0, max_iters=8,
+        s = gpu_solver(shape, h, st, al, Q, precision=precision, tol=0.0, max_iters=8,
                        omega_s=omega_s, colour_split=split)
         outs.append(s.solve())
     np.testing.assert_array_equal(outs[1][0], outs[0][0])
