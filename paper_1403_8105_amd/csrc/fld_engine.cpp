@@ -1186,10 +1186,10 @@ struct fld_engine_impl {
         }
         if (first)
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal, k & 1,
-                           k & 1, 0, 0, 0, kmode);
+                           k & 1, 0, 0, 0, kmode, opt.limiter);
         else
             launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, d_active, d_scal,
-                           (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, kmode);
+                           (k - 1) & 1, k & 1, 1, (k - 1) & 1, 0, kmode, opt.limiter);
         // limiter: phi and sig_hat read, D written (FP64, plus the smoother's
         // copy: FP32 in the mixed form, colour-split FP64 in the FP64 form);
         // with the direction update also p read, phi written
@@ -1411,7 +1411,7 @@ struct fld_engine_impl {
         for (;;) {
             if ((it - first) % every == 0 || it - first == opt.max_iters) {
                 launch_limiter(stream, d_fines, fine_tasks.d, fine_tasks.n, nullptr, d_scal, 0, 0, 0,
-                               0, 1, 0);
+                               0, 1, 0, opt.limiter);
                 launch_residual(stream, d_fines, fine_tasks.d, fine_tasks.n, nullptr, 0, 1, 0,
                                 nullptr, d_part[0], 0);
                 launch_sum_partials(stream, 1, d_fine_range, d_part[0], d_scal, S_RES2, nullptr);
@@ -1944,7 +1944,7 @@ static fld_status residual_impl(fld_context *c, const double *phi, bool dev, dou
         f.b0[0] = f.b0[1] = ws->b;
         launch_put_fine(E.stream, f, ws->fine);
         launch_limiter(E.stream, ws->fine, E.fine_tasks.d, E.fine_tasks.n, nullptr, E.d_scal, 0,
-                       0, 0, 0, 1, 0);
+                       0, 0, 0, 1, 0, E.opt.limiter);
         launch_residual(E.stream, ws->fine, E.fine_tasks.d, E.fine_tasks.n, nullptr, 0, 1, 0,
                         r_out, E.d_part[0], 0);
         launch_sum_partials(E.stream, 1, E.d_fine_range, E.d_part[0], E.d_scal, S_AUX, nullptr);
@@ -1977,7 +1977,7 @@ static fld_status residual_impl(fld_context *c, const double *phi, bool dev, dou
     f.b0[0] = f.b0[1] = tb;
     hipMemcpyAsync(dfine, &f, sizeof(Fine), hipMemcpyHostToDevice, E.stream);
     launch_limiter(E.stream, dfine, E.fine_tasks.d, E.fine_tasks.n, nullptr, E.d_scal, 0, 0, 0, 0,
-                   1, 0);
+                   1, 0, E.opt.limiter);
     launch_residual(E.stream, dfine, E.fine_tasks.d, E.fine_tasks.n, nullptr, 0, 1, 0, tr,
                     E.d_part[0], 0);
     launch_sum_partials(E.stream, 1, E.d_fine_range, E.d_part[0], E.d_scal, S_AUX, nullptr);

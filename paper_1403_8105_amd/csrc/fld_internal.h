@@ -141,9 +141,11 @@ void launch_sum_partials(hipStream_t s, int nprob, const int *range, const doubl
 void launch_after_setup(hipStream_t s, int nprob, const Fine *fines, double *scal);
 void launch_init_phi(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                      const double *scal, int zero_dirs, int mixed);
+// lim_kind: the limiter of every grid in the list (an LP-only kernel instance
+// is launched for L_LP), or -1 when they differ
 void launch_limiter(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                     const int *active, const double *scal, int src, int dst, int use_dir,
-                    int dir_idx, int to_tmp, int mixed);
+                    int dir_idx, int to_tmp, int mixed, int lim_kind);
 void launch_residual(hipStream_t s, const Fine *fines, const Task *tasks, int ntasks,
                      const int *active, int src, int use_tmp, int b0_idx, double *r_out,
                      double *partials, int mixed);
