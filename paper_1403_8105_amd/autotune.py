@@ -1,6 +1,7 @@
-"""Autotuner of the multigrid solve: launch shapes and smoothing schedule.
+"""Autotuner of the multigrid solve: launch shapes, smoothing schedule, outer
+step and pass forms.
 
-Two phases, both timed on the GPU through the C ABI with the inputs resident
+Four phases, all timed on the GPU through the C ABI with the inputs resident
 in device memory:
 
 1. Launch shapes (``task_cells0``, ``coarse_blocks``).  They change no result
@@ -21,6 +22,14 @@ in device memory:
    and correction factors with the best window (the best smoothing schedule
    changes with the outer step), the regularisation, and how far the coarser
    problem is solved first.  Starting from the cached entry it runs alone.
+4. Pass forms, with the winner's options: the finest level's red and black
+   half-sweeps fused into single LDS-tiled sweeps (``fuse_rb``) and the
+   limiter and residual fused into one pass (``fuse_lr``), each on or off.
+   Like the launch shapes they leave the iteration as it is (``fuse_lr``
+   regroups the partial sums of the residual norm only), so a capped solve per
+   form gives the time per outer iteration; the fastest is kept, and the
+   times are stored with the entry.  ``passes_only`` runs this phase alone on
+   a cached entry and keeps its other options.
 
 The winner is cached as JSON, keyed by (GPU architecture, grid, precision,
 limiter), in ``tuned.json`` beside this file unless another path is given.
@@ -56,6 +65,7 @@ AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.
                 (6, 6, 1.15), (4, 4, 1.25)]
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 AA_NESTED = [3e-3, 1e-2, 3e-2, 1e-1]   # grid sequencing with the chosen window
+PASSES = [(0, 0), (1, 0), (0, 1), (1, 1)]   # (fuse_rb, fuse_lr)
 
 
 def cache_key(arch: str, shape, precision: str, limiter: str, tol: float | None = None) -> str:
@@ -90,6 +100,29 @@ def tuned_options(shape, precision: str = "mixed", limiter: str = "lp", arch: st
     return dict(entry["options"]) if entry else {}
 
 
+def _pass_forms(F, st, h, ptrs, d_phi, stream, opts, probe_iters, log):
+    """Time per outer iteration of each pass form with the options ``opts``
+    (grid sequencing off, so that only fine iterations are timed)."""
+    out = {}
+    for rb, lr in PASSES:
+        o = dict(opts, tol=0.0, max_iters=probe_iters, nested_tol=0.0, fuse_rb=rb, fuse_lr=lr)
+        _solve_ms(F, st, h, ptrs, d_phi, stream, o)      # warm
+        ms, rep = _solve_ms(F, st, h, ptrs, d_phi, stream, o)
+        out[(rb, lr)] = ms / max(rep["iterations"], 1)
+        log(f"autotune: fuse_rb={rb} fuse_lr={lr}: {out[(rb, lr)]:.4f} ms/it")
+    return out
+
+
+def _apply_passes(opts: dict, pass_ms: dict) -> dict:
+    rb, lr = min(pass_ms, key=pass_ms.get)
+    opts = {k: v for k, v in opts.items() if k not in ("fuse_rb", "fuse_lr")}
+    if rb:
+        opts["fuse_rb"] = 1
+    if lr:
+        opts["fuse_lr"] = 1
+    return opts
+
+
 def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
     """One device solve; returns (wall ms, report)."""
     import torch
@@ -110,7 +143,7 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
          probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
          quick: bool = False, refine: bool = False, schedules=None, scales=None,
-         anderson: bool = False, tol_key: bool = False) -> dict:
+         anderson: bool = False, tol_key: bool = False, passes_only: bool = False) -> dict:
     """Tune one grid/medium; stores and returns the cache entry.  ``schedules``
     ((nu1, nu2, omega_s, restart_growth) tuples) and ``scales`` replace the
     default candidate lists (for grids whose full search is too long).
@@ -135,6 +168,21 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         old = cache0.get(cache_key(device_arch(), sigma_t.shape, precision, limiter))
     if refine and not old:
         raise RuntimeError(f"autotune: --refine needs a cached entry for {key}")
+    if passes_only:
+        # phase 4 alone on the cached entry
+        entry = cache0.get(key)
+        if not entry:
+            raise RuntimeError(f"autotune: --passes-only needs a cached entry for {key}")
+        pass_ms = _pass_forms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream,
+                              dict(base, **entry["options"]), probe_iters, log)
+        entry = dict(entry, options=_apply_passes(entry["options"], pass_ms),
+                     pass_ms_per_iteration={f"{a},{b}": v for (a, b), v in pass_ms.items()})
+        if path:
+            cache = load_cache(path)
+            cache[key] = entry
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        return entry
 
     # phase 1: launch shapes, time per outer iteration of a capped solve
     shape_ms = {}
@@ -247,12 +295,17 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         opts["aa_m"] = best["aa_m"]
         if best.get("aa_reg", 1e-10) != 1e-10:
             opts["aa_reg"] = best["aa_reg"]
+    # phase 4: pass forms with the winner's options
+    pass_ms = _pass_forms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, dict(base, **opts),
+                          probe_iters, log)
+    opts = _apply_passes(opts, pass_ms)
     entry = {
         "options": opts,
         "tol": tol,
         "ms_to_tol": best["ms"],
         "iterations": best["iterations"],
         "shape_ms_per_iteration": {f"{a},{b}": v for (a, b), v in shape_ms.items()},
+        "pass_ms_per_iteration": {f"{a},{b}": v for (a, b), v in pass_ms.items()},
         "schedules": (cache0[key].get("schedules", []) if refine and key in cache0 else [])
                      + results,
     }
@@ -403,6 +456,9 @@ def main(argv=None):
     ap.add_argument("--tol-key", action="store_true",
                     help="store the entry under a key naming --tol (a separate entry for a "
                          "tight tolerance)")
+    ap.add_argument("--passes-only", action="store_true",
+                    help="time the fused and separate pass forms with the cached entry's "
+                         "options and keep the fastest (no other option changes)")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from synth import media
@@ -422,9 +478,11 @@ def main(argv=None):
     entry = tune(st, al, Q, h, precision=args.precision, limiter=args.limiter, tol=args.tol,
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
                  max_iters=args.max_iters, refine=args.refine, schedules=schedules,
-                 scales=scales, anderson=args.anderson, tol_key=args.tol_key)
+                 scales=scales, anderson=args.anderson, tol_key=args.tol_key,
+                 passes_only=args.passes_only)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
-                      "iterations": entry["iterations"]}), flush=True)
+                      "iterations": entry["iterations"],
+                      "pass_ms_per_iteration": entry.get("pass_ms_per_iteration")}), flush=True)
 
 
 if __name__ == "__main__":
