@@ -163,6 +163,13 @@ typedef struct fld_options {
                              every problem's phi after the residual of outer iteration k
                              is read, so the next residual is not finite and the solve
                              ends with FLD_ERR_DIVERGED at iteration k+1; 0 (default) off  */
+    int nu_coarse;        /* multigrid: pre- and post-smoothing sweeps on every level from
+                             coarse_from on (level 0 is the finest; the coarsest is solved,
+                             not smoothed); 0 (default) keeps nu1 / nu2 there.  In [0,64].
+                             The small levels cost little per sweep (their launches are
+                             latency-bound), and a better coarse correction saves outer
+                             iterations                                                    */
+    int coarse_from;      /* first level that nu_coarse applies to, >= 1 (default 2)      */
 } fld_options;
 
 typedef struct fld_report {

@@ -39,7 +39,8 @@ class SolveOpts(C.Structure):
                 ("max_iters", C.c_int), ("tol", C.c_double), ("check_every", C.c_int),
                 ("theta", C.c_double), ("step_mode", C.c_int), ("deflate_tau", C.c_double),
                 ("restart_growth", C.c_double), ("corr_scale", C.c_double),
-                ("aa_m", C.c_int), ("aa_reg", C.c_double)]
+                ("aa_m", C.c_int), ("aa_reg", C.c_double), ("nu_coarse", C.c_int),
+                ("coarse_from", C.c_int)]
 
 
 class Result(C.Structure):
@@ -257,14 +258,16 @@ def clusters(prob: Problem, tau: float = 1.0):
 def solve_opts(method="mg", omega=1.0, omega_s=1.0, nu1=2, nu2=2, max_coarsest=512,
                max_iters=1000, tol=1e-6, check_every=1, theta=1.0,
                step="optimal", deflate_tau=1.0, restart_growth=2.0,
-               corr_scale=1.0, aa_m=0, aa_reg=1e-10) -> SolveOpts:
+               corr_scale=1.0, aa_m=0, aa_reg=1e-10, nu_coarse=0, coarse_from=2) -> SolveOpts:
     if not 0 <= aa_m <= 16:
         raise ValueError("aa_m must lie in [0, 16]")
+    if nu_coarse < 0 or coarse_from < 1:
+        raise ValueError("nu_coarse must be >= 0 and coarse_from >= 1")
     return SolveOpts(METHODS[method], float(omega), float(omega_s), int(nu1), int(nu2),
                      int(max_coarsest), int(max_iters), float(tol), int(check_every),
                      float(theta), {"fixed": 0, "optimal": 1, "optimal-norestart": 2}[step],
                      float(deflate_tau), float(restart_growth), float(corr_scale), int(aa_m),
-                     float(aa_reg))
+                     float(aa_reg), int(nu_coarse), int(coarse_from))
 
 
 def linear_vcycle(D, sa, b, h, d_ghost, mirror=False, **kw):

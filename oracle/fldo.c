@@ -616,8 +616,9 @@ static void assemble_level(const mg_level *L, double d_ghost, int mirror, double
             }
 }
 
-/* V(nu1, nu2) cycle on levels[l..nlev-1].  Every level starts from a zero
- * correction, except the first when e_start is given: its smoothing then
+/* V(nu1, nu2) cycle on levels[l..nlev-1] (nu_coarse sweeps before and after
+ * on the levels from coarse_from on, when set).  Every level starts from a
+ * zero correction, except the first when e_start is given: its smoothing then
  * starts from e_start (the cluster deflation step). */
 static void vcycle(mg_level *lv, int l, int nlev, const fldo_solve_opts *o, double d_ghost,
                    int mirror, const double *chol, const double *e_start)
@@ -637,7 +638,9 @@ static void vcycle(mg_level *lv, int l, int nlev, const fldo_solve_opts *o, doub
         memcpy(L->e, e_start, sizeof(double) * n);
     else
         memset(L->e, 0, sizeof(double) * n);
-    for (int s = 0; s < o->nu1; ++s) {
+    const int coarse = l >= 1 && o->nu_coarse > 0 && l >= o->coarse_from;
+    const int pre = coarse ? o->nu_coarse : o->nu1, post = coarse ? o->nu_coarse : o->nu2;
+    for (int s = 0; s < pre; ++s) {
         level_smooth_colour(L, d_ghost, mirror, 0, o->omega_s);
         level_smooth_colour(L, d_ghost, mirror, 1, o->omega_s);
     }
@@ -645,7 +648,7 @@ static void vcycle(mg_level *lv, int l, int nlev, const fldo_solve_opts *o, doub
     mean8(lv[l + 1].nx, lv[l + 1].ny, lv[l + 1].nz, L->ny, L->nz, L->r, lv[l + 1].b);
     vcycle(lv, l + 1, nlev, o, d_ghost, mirror, chol, NULL);
     prolong_add(&lv[l + 1], L, l == 0 ? o->corr_scale : 1.0);
-    for (int s = 0; s < o->nu2; ++s) {
+    for (int s = 0; s < post; ++s) {
         level_smooth_colour(L, d_ghost, mirror, 1, o->omega_s);
         level_smooth_colour(L, d_ghost, mirror, 0, o->omega_s);
     }

@@ -64,6 +64,9 @@ typedef struct fldo_solve_opts {
                                  clears its history) */
     double aa_reg;            /* Anderson: Tikhonov weight relative to the mean diagonal of
                                  the Gram matrix */
+    int nu_coarse;            /* > 0: pre- and post-sweeps on every level l >= coarse_from
+                                 (l = 0 the finest) instead of nu1 / nu2 */
+    int coarse_from;          /* first level of nu_coarse, >= 1 */
 } fldo_solve_opts;
 
 typedef struct fldo_result {

@@ -22,6 +22,10 @@ in device memory:
    and correction factors with the best window (the best smoothing schedule
    changes with the outer step), the regularisation, and how far the coarser
    problem is solved first.  Starting from the cached entry it runs alone.
+   ``coarse`` then tries extra smoothing sweeps on the coarse levels
+   (``nu_coarse`` from level ``coarse_from`` on) for the winner and, with an
+   Anderson window, the windows again; with ``refine`` it starts from the
+   cached entry and runs alone.
 4. Pass forms, with the winner's options: the finest level's red and black
    half-sweeps fused into single LDS-tiled sweeps (``fuse_rb``) and the
    limiter and residual fused into one pass (``fuse_lr``), each on or off.
@@ -65,6 +69,7 @@ AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.
                 (6, 6, 1.15), (4, 4, 1.25)]
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 AA_NESTED = [3e-3, 1e-2, 3e-2, 1e-1]   # grid sequencing with the chosen window
+COARSE_SWEEPS = [(8, 2), (12, 2), (16, 2), (24, 2), (12, 1), (16, 1), (16, 3), (24, 3)]
 PASSES = [(0, 0), (1, 0), (0, 1), (1, 1)]   # (fuse_rb, fuse_lr)
 
 
@@ -143,7 +148,8 @@ def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
 def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
          probe_iters: int = 40, max_iters: int = 5000, path: str | None = CACHE, log=print,
          quick: bool = False, refine: bool = False, schedules=None, scales=None,
-         anderson: bool = False, tol_key: bool = False, passes_only: bool = False) -> dict:
+         anderson: bool = False, tol_key: bool = False, passes_only: bool = False,
+         coarse: bool = False) -> dict:
     """Tune one grid/medium; stores and returns the cache entry.  ``schedules``
     ((nu1, nu2, omega_s, restart_growth) tuples) and ``scales`` replace the
     default candidate lists (for grids whose full search is too long).
@@ -204,22 +210,32 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     # full solves to tol
     results = []
 
-    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0, reg=1e-10):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0, reg=1e-10, nc=0, cf=2):
         o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
                  nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc, nested_tol=nt,
-                 aa_m=aa, aa_reg=reg)
+                 aa_m=aa, aa_reg=reg, nu_coarse=nc, coarse_from=cf)
         ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg, "ms": ms,
+                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg,
+                        "nu_coarse": nc, "coarse_from": cf, "ms": ms,
                         "iterations": rep["iterations"],
                         "nested_iterations": rep.get("nested_iterations", 0),
                         "rel": rep["rel"], "converged": ok})
         log(f"autotune: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} corr_scale={sc} "
-            f"nested_tol={nt} aa_m={aa}: {rep['iterations']} its "
+            f"nested_tol={nt} aa_m={aa} nu_coarse={nc}@{cf}: {rep['iterations']} its "
             f"(+{rep.get('nested_iterations', 0)} coarse), rel {rep['rel']:.2e}, {ms:.0f} ms"
             f"{'' if ok else ' (not converged)'}")
         return results[-1] if ok else None
+
+    def again(b, **over):
+        """run() with the options of result b, some replaced"""
+        p = dict(nu1=b["nu1"], nu2=b["nu2"], ws=b["omega_s"], gr=b["restart_growth"],
+                 sc=b["corr_scale"], nt=b.get("nested_tol", 0.0), aa=b.get("aa_m", 0),
+                 reg=b.get("aa_reg", 1e-10), nc=b.get("nu_coarse", 0),
+                 cf=b.get("coarse_from", 2))
+        p.update(over)
+        return run(**p)
 
     def better(a, b):
         return a if b is None or (a is not None and a["ms"] < b["ms"]) else b
@@ -228,24 +244,25 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     if old:
         oo = old["options"]
         best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"],
-                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0), oo.get("aa_reg", 1e-10))
+                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0), oo.get("aa_reg", 1e-10),
+                   oo.get("nu_coarse", 0), oo.get("coarse_from", 2))
     elif quick:
         best = run(*DEFAULT_SCHEDULE, 1.0)
     else:
         cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
         for nu1, nu2, ws, gr in cands:
             best = better(run(nu1, nu2, ws, gr, (scales or SCALES)[0]), best)
-    if best is None and not (old and anderson):
+    if best is None and not (old and (anderson or coarse)):
         raise RuntimeError("autotune: no schedule reached the tolerance")
     if not old:
         for sc in (scales or SCALES)[1:]:
             best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
                               sc), best)
-    if even and not (old and anderson):
+    if even and not (old and (anderson or coarse)):
         for nt in NESTED:
             best = better(run(best["nu1"], best["nu2"], best["omega_s"], best["restart_growth"],
                               best["corr_scale"], nt), best)
-    if anderson:
+    if anderson and not (old and coarse):
         # phase 3: Anderson windows for the winner, then schedules and
         # correction factors with the best window.  Anderson acceleration needs
         # a start near the solution: without grid sequencing in the winner,
@@ -284,6 +301,16 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                         best = better(run(b4["nu1"], b4["nu2"], b4["omega_s"],
                                           b4["restart_growth"], b4["corr_scale"], nt, b4["aa_m"],
                                           b4.get("aa_reg", 1e-10)), best)
+    if coarse and best is not None:
+        # extra sweeps on the coarse levels, then (with a window) the windows again
+        b5 = best
+        for nc, cf in COARSE_SWEEPS:
+            best = better(again(b5, nc=nc, cf=cf), best)
+        if best is not b5 and best.get("aa_m"):
+            b6 = best
+            for m in AA_WINDOWS:
+                if m != b6["aa_m"]:
+                    best = better(again(b6, aa=m), best)
     if best is None:
         raise RuntimeError("autotune: no candidate reached the tolerance")
     opts = {"task_cells0": tc0, "coarse_blocks": cb, "nu1": best["nu1"], "nu2": best["nu2"],
@@ -295,6 +322,9 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         opts["aa_m"] = best["aa_m"]
         if best.get("aa_reg", 1e-10) != 1e-10:
             opts["aa_reg"] = best["aa_reg"]
+    if best.get("nu_coarse"):
+        opts["nu_coarse"] = best["nu_coarse"]
+        opts["coarse_from"] = best["coarse_from"]
     # phase 4: pass forms with the winner's options
     pass_ms = _pass_forms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, dict(base, **opts),
                           probe_iters, log)
@@ -330,7 +360,8 @@ def batch_options(precision: str = "mixed", limiter: str = "lp", arch: str | Non
 
 def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
                max_iters: int = 5000, path: str | None = CACHE, log=print, schedules=None,
-               scales=None, anderson: bool = False, refine: bool = False) -> dict:
+               scales=None, anderson: bool = False, refine: bool = False,
+               coarse: bool = False) -> dict:
     """Schedule search on the batched workload (``synth.media.batch_config``: 16
     cloud volumes x 3 colour channels): every candidate is one whole batched
     solve to the tolerance, default launch shapes; the shortest wins.  Grid
@@ -344,11 +375,11 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     allow = (F.FLD_OK, F.FLD_ERR_NOT_CONVERGED, F.FLD_ERR_DIVERGED)
     results = []
 
-    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0, reg=1e-10):
+    def run(nu1, nu2, ws, gr, sc, nt=0.0, aa=0, reg=1e-10, nc=0, cf=2):
         o = F.fld_default_options(precision=precision, limiter=limiter, tol=tol,
                                   max_iters=max_iters, nu1=nu1, nu2=nu2, omega_s=ws,
                                   restart_growth=gr, corr_scale=sc, nested_tol=nt, aa_m=aa,
-                                  aa_reg=reg)
+                                  aa_reg=reg, nu_coarse=nc, coarse_from=cf)
         b = F.fld_batch_create(o, dims, [v["h"] for v in vols], 3)
         try:
             for q, v in enumerate(vols):
@@ -360,10 +391,12 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
             F.fld_batch_destroy(b)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
-                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg, "ms": ms,
+                        "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg,
+                        "nu_coarse": nc, "coarse_from": cf, "ms": ms,
                         "iterations_max": int(its.max()), "converged": ok})
         log(f"autotune batch: nu=({nu1},{nu2}) omega_s={ws} restart_growth={gr} "
-            f"corr_scale={sc} nested_tol={nt} aa_m={aa}: iterations {its.min()}..{its.max()} "
+            f"corr_scale={sc} nested_tol={nt} aa_m={aa} nu_coarse={nc}@{cf}: "
+            f"iterations {its.min()}..{its.max()} "
             f"(+{rep.get('nested_iterations', 0)} coarse), {ms:.0f} ms"
             f"{'' if ok else ' (not converged)'}")
         return results[-1] if ok else None
@@ -380,7 +413,8 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     if old:
         oo = old["options"]
         best = run(oo["nu1"], oo["nu2"], oo["omega_s"], oo["restart_growth"], oo["corr_scale"],
-                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0), oo.get("aa_reg", 1e-10))
+                   oo.get("nested_tol", 0.0), oo.get("aa_m", 0), oo.get("aa_reg", 1e-10),
+                   oo.get("nu_coarse", 0), oo.get("coarse_from", 2))
     else:
         cands = schedules or [(nu1, nu2, ws, gr) for nu1, nu2, ws in SCHEDULES for gr in GROWTHS]
         for nu1, nu2, ws, gr in cands:
@@ -395,7 +429,16 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
             for nt in NESTED:
                 best = better(run(best["nu1"], best["nu2"], best["omega_s"],
                                   best["restart_growth"], best["corr_scale"], nt), best)
-    if anderson:
+
+    def again(b, **over):
+        p = dict(nu1=b["nu1"], nu2=b["nu2"], ws=b["omega_s"], gr=b["restart_growth"],
+                 sc=b["corr_scale"], nt=b.get("nested_tol", 0.0), aa=b.get("aa_m", 0),
+                 reg=b.get("aa_reg", 1e-10), nc=b.get("nu_coarse", 0),
+                 cf=b.get("coarse_from", 2))
+        p.update(over)
+        return run(**p)
+
+    if anderson and not (old and coarse):
         b0 = best
         for m in AA_WINDOWS:
             best = better(run(b0["nu1"], b0["nu2"], b0["omega_s"], b0["restart_growth"],
@@ -416,9 +459,19 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
                     best = better(run(b4["nu1"], b4["nu2"], b4["omega_s"], b4["restart_growth"],
                                       b4["corr_scale"], nt, b4["aa_m"], b4.get("aa_reg", 1e-10)),
                                   best)
+    if coarse:
+        b5 = best
+        for nc, cf in COARSE_SWEEPS:
+            best = better(again(b5, nc=nc, cf=cf), best)
+        if best is not b5 and best.get("aa_m"):
+            b6 = best
+            for m in AA_WINDOWS:
+                if m != b6["aa_m"]:
+                    best = better(again(b6, aa=m), best)
     keys = ("nu1", "nu2", "omega_s", "restart_growth", "corr_scale") + \
         (("nested_tol",) if best["nested_tol"] else ()) + (("aa_m",) if best.get("aa_m") else ()) + \
-        (("aa_reg",) if best.get("aa_m") and best.get("aa_reg", 1e-10) != 1e-10 else ())
+        (("aa_reg",) if best.get("aa_m") and best.get("aa_reg", 1e-10) != 1e-10 else ()) + \
+        (("nu_coarse", "coarse_from") if best.get("nu_coarse") else ())
     entry = {"options": {k: best[k] for k in keys},
              "tol": tol, "ms_to_tol": best["ms"], "iterations_max": best["iterations_max"],
              "schedules": results}
@@ -456,6 +509,9 @@ def main(argv=None):
     ap.add_argument("--tol-key", action="store_true",
                     help="store the entry under a key naming --tol (a separate entry for a "
                          "tight tolerance)")
+    ap.add_argument("--coarse", action="store_true",
+                    help="also try extra sweeps on the coarse levels (with --refine: only "
+                         "that, from the cached entry)")
     ap.add_argument("--passes-only", action="store_true",
                     help="time the fused and separate pass forms with the cached entry's "
                          "options and keep the fastest (no other option changes)")
@@ -470,7 +526,8 @@ def main(argv=None):
         entry = tune_batch(precision=args.precision, limiter=args.limiter, tol=args.tol,
                            max_iters=args.max_iters, path=args.out,
                            log=lambda m: print(m, flush=True), schedules=schedules,
-                           scales=scales, anderson=args.anderson, refine=args.refine)
+                           scales=scales, anderson=args.anderson, refine=args.refine,
+                           coarse=args.coarse)
         print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"]}),
               flush=True)
         return
@@ -479,7 +536,7 @@ def main(argv=None):
                  path=args.out, log=lambda m: print(m, flush=True), quick=args.quick,
                  max_iters=args.max_iters, refine=args.refine, schedules=schedules,
                  scales=scales, anderson=args.anderson, tol_key=args.tol_key,
-                 passes_only=args.passes_only)
+                 passes_only=args.passes_only, coarse=args.coarse)
     print(json.dumps({"options": entry["options"], "ms_to_tol": entry["ms_to_tol"],
                       "iterations": entry["iterations"],
                       "pass_ms_per_iteration": entry.get("pass_ms_per_iteration")}), flush=True)

@@ -219,7 +219,7 @@ struct fld_engine_impl {
     {
         if (!opt.timing)
             return;
-        const size_t need = 2 * (size_t)(2 * (opt.nu1 + opt.nu2) + 3);
+        const size_t need = 2 * (size_t)(2 * (opt.nu1 + opt.nu2) + 3);   // finest level only
         while (graph_spare.size() < need) {
             hipEvent_t e = nullptr;
             if (hipEventCreate(&e) != hipSuccess) {
@@ -384,6 +384,16 @@ struct fld_engine_impl {
     {
         for (long long s = 0; s < n; s += cells)
             v.push_back(Task{grid, (int)std::min<long long>(cells, n - s), s});
+    }
+    // Smoothing sweeps of level l (0 = finest) before (pre) or after the coarse
+    // correction: nu_coarse on the levels from coarse_from on when it is set,
+    // else nu1 / nu2.  The rule goes by level index, so every problem of a
+    // batch sweeps its level l as often as it would alone.
+    int sweeps(int l, bool pre) const
+    {
+        if (l >= 1 && opt.nu_coarse > 0 && l >= opt.coarse_from)
+            return opt.nu_coarse;
+        return pre ? opt.nu1 : opt.nu2;
     }
     // Largest power-of-two task size in [lo, kTaskCells] that still yields
     // opt.coarse_blocks tasks for n cells.
@@ -630,6 +640,8 @@ struct fld_engine_impl {
                 g.e = L.e; g.b = L.b; g.sa = L.sa; g.D = l == 0 ? P.fine.D0 : nullptr; g.f = L.f;
                 g.e2 = L.e2;
                 g.band = L.band;
+                g.nu_pre = (short)sweeps(l, true);
+                g.nu_post = (short)sweeps(l, false);
                 grids[0].push_back(g);
                 if (l == 0)
                     g.b = P.fine.b0[1];
@@ -1096,7 +1108,7 @@ struct fld_engine_impl {
                         smooth_rb<T>(G, 0, 0);
                         smooth_rb<T>(G, 0, 1);
                     }
-                for (; s < opt.nu1; ++s) {
+                for (; s < sweeps(l, true); ++s) {
                     smooth<T>(G, l, 0);
                     smooth<T>(G, l, 1);
                 }
@@ -1105,12 +1117,12 @@ struct fld_engine_impl {
         }
         // join: the coarsest factors are complete
         note(hipStreamWaitEvent(stream, ev_join, 0), "hipStreamWaitEvent");
-        launch_tail<T>(stream, G, d_tail_roots, n_tail, d_active, d_fail, opt.nu1, opt.nu2,
-                       opt.omega_s, (int)tail_lds);
-        launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.nu1, opt.omega_s, true);
+        launch_tail<T>(stream, G, d_tail_roots, n_tail, d_active, d_fail, opt.omega_s,
+                       (int)tail_lds);
+        launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.omega_s, true);
         launch_coarse_solve<T>(stream, G, d_coarse_ids, n_coarse, d_active, d_fail, max_coarse_n,
                                max_coarse_bw);
-        launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.nu2, opt.omega_s, false);
+        launch_deep<T>(stream, G, d_deep_roots, n_deep, d_active, opt.omega_s, false);
         for (int l = max_levels - 2; l >= 0; --l) {
             if (!mid[l].n)
                 continue;
@@ -1122,7 +1134,7 @@ struct fld_engine_impl {
                     smooth_rb<T>(G, 1, 0);
                     smooth_rb<T>(G, 1, 1);
                 }
-            for (; s < opt.nu2; ++s) {
+            for (; s < sweeps(l, false); ++s) {
                 smooth<T>(G, l, 1);
                 smooth<T>(G, l, 0);
             }
@@ -1134,7 +1146,7 @@ struct fld_engine_impl {
         double u = 0.0;
         for (const Prob &P : probs)
             for (int l = 0; l + 1 < P.nlev; ++l)
-                u += (double)P.lv[l].n * (opt.nu1 + opt.nu2);
+                u += (double)P.lv[l].n * (sweeps(l, true) + sweeps(l, false));
         return u;
     }
 
@@ -1356,7 +1368,8 @@ struct fld_engine_impl {
             for (int p = 0; p < N; ++p)
                 if (h_active[p])
                     for (int l = 0; l + 1 < probs[p].nlev; ++l)
-                        *updates += (double)probs[p].lv[l].n * (opt.nu1 + opt.nu2);
+                        *updates += (double)probs[p].lv[l].n *
+                                    (sweeps(l, true) + sweeps(l, false));
             replayed = -1;
             const int par = k & 1;
             const bool use_graph = k >= 1 && opt.graph && graphs_ok;
@@ -1516,6 +1529,8 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->fuse_lr != 0 && o->fuse_lr != 1) { err = "fuse_lr must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->fuse_rb != 0 && o->fuse_rb != 1) { err = "fuse_rb must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->debug_nan_iter < 0) { err = "debug_nan_iter must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->nu_coarse < 0 || o->nu_coarse > 64) { err = "nu_coarse must lie in [0,64]"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->coarse_from < 1) { err = "coarse_from must be >= 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->aa_reg >= 0.0 && std::isfinite(o->aa_reg))) { err = "aa_reg must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
@@ -1632,6 +1647,8 @@ fld_status fld_default_options(fld_options *o)
     o->fuse_lr = 0;
     o->fuse_rb = 0;
     o->debug_nan_iter = 0;
+    o->nu_coarse = 0;
+    o->coarse_from = 2;
     return FLD_OK;
 }
 

@@ -35,7 +35,8 @@ struct Grid {
     int finer;       // index of the next finer grid in the same table (-1: none)
     int coarser;     // index of the next coarser grid (-1: none)
     int split;       // e, b, sa, D stored colour by colour (see Fine::split)
-    int pad;
+    short nu_pre;    // smoothing sweeps of this level before the coarse correction
+    short nu_post;   // and after it
     void *e, *b, *sa, *D, *f;
     void *e2;        // finest level: second correction buffer of the fused sweep
     double *band;    // coarsest level: banded Cholesky factor of h^2 A, n*(ny*nz+1)
@@ -228,12 +229,12 @@ void launch_mean8_sa(hipStream_t s, const Grid *grids, const Task *tasks, int nt
 // Coarsest level: one block per listed grid.  fail[prob] is set to 1 when a
 // pivot is not positive.
 // Deep part of the V-cycle, one workgroup per root (the first level of a
-// problem at or below the deep size limit): down (zero, nu pre-sweeps,
-// restrict) or up (prolong, nu post-sweeps) over the levels above the
-// coarsest.
+// problem at or below the deep size limit): down (zero, Grid::nu_pre
+// pre-sweeps, restrict) or up (prolong, Grid::nu_post post-sweeps) over the
+// levels above the coarsest.
 template <typename T>
 void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
-                 int nu, double omega, bool down);
+                 double omega, bool down);
 template <typename T>
 void launch_coarse_solve(hipStream_t s, const Grid *grids, const int *ids, int count,
                          const int *active, int *fail, int max_n, int max_bw);
@@ -269,7 +270,7 @@ void launch_coarse_factor(hipStream_t s, const Grid *grids, const int *ids, int 
 // tail_lds_limit().
 template <typename T>
 void launch_tail(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
-                 int *fail, int nu1, int nu2, double omega, int lds_bytes);
+                 int *fail, double omega, int lds_bytes);
 long long tail_lds_need(long long nc, long long bw, long long deep_cells, long long scratch_cells,
                         int tsz);
 int tail_lds_limit();

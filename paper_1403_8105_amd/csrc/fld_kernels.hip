@@ -2775,11 +2775,11 @@ __device__ void deep_prolong(const Grid &F, const Grid &C)
     }
 }
 
-// Down: from the root, zero e, nu1 pre-sweeps (red then black), restrict,
-// to the level above the coarsest.
+// Down: from the root, zero e, the level's pre-sweeps (red then black),
+// restrict, to the level above the coarsest.
 template <typename T>
 __global__ void __launch_bounds__(kDeepBlock)
-k_deep_down(const Grid *grids, const int *roots, const int *active, int nu1, T omega)
+k_deep_down(const Grid *grids, const int *roots, const int *active, T omega)
 {
     int gid = roots[blockIdx.x];
     if (active && !active[grids[gid].prob])
@@ -2788,7 +2788,7 @@ k_deep_down(const Grid *grids, const int *roots, const int *active, int nu1, T o
         const Grid &g = grids[gid];
         deep_zero<T>(g);
         __syncthreads();
-        for (int s = 0; s < nu1; ++s) {
+        for (int s = 0; s < g.nu_pre; ++s) {
             deep_smooth<T>(g, 0, omega);
             __syncthreads();
             deep_smooth<T>(g, 1, omega);
@@ -2801,10 +2801,10 @@ k_deep_down(const Grid *grids, const int *roots, const int *active, int nu1, T o
 }
 
 // Up: from the level above the coarsest back to the root, prolongate and
-// nu2 post-sweeps (black then red).
+// the level's post-sweeps (black then red).
 template <typename T>
 __global__ void __launch_bounds__(kDeepBlock)
-k_deep_up(const Grid *grids, const int *roots, const int *active, int nu2, T omega)
+k_deep_up(const Grid *grids, const int *roots, const int *active, T omega)
 {
     const int root = roots[blockIdx.x];
     if (active && !active[grids[root].prob])
@@ -2817,7 +2817,7 @@ k_deep_up(const Grid *grids, const int *roots, const int *active, int nu2, T ome
         const Grid &g = grids[gid];
         deep_prolong<T>(g, grids[g.coarser]);
         __syncthreads();
-        for (int s = 0; s < nu2; ++s) {
+        for (int s = 0; s < g.nu_post; ++s) {
             deep_smooth<T>(g, 1, omega);
             __syncthreads();
             deep_smooth<T>(g, 0, omega);
@@ -3283,8 +3283,7 @@ __host__ __device__ inline long long tail_lds_bytes(long long nc, long long bw, 
 
 template <typename T>
 __global__ void __launch_bounds__(kTailBlock)
-k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail, int nu1, int nu2,
-              T omega)
+k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail, T omega)
 {
     extern __shared__ double lds[];
     const int root = roots[blockIdx.x];
@@ -3323,12 +3322,12 @@ k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail,
     if (nd == 0)
         for (int c = threadIdx.x; c < nc; c += kTailBlock)
             y[c] = (double)((const T *)Cg.b)[c] * Cg.h2;
-    // down: zero, nu1 pre-sweeps (red then black), restrict
+    // down: zero, the level's pre-sweeps (red then black), restrict
     for (int l = 0; l < nd; ++l) {
         const Grid &g = grids[lv[l]];
         tail_zero<T>(g, e[l]);
         __syncthreads();
-        for (int s = 0; s < nu1; ++s)
+        for (int s = 0; s < g.nu_pre; ++s)
             for (int colour = 0; colour < 2; ++colour) {
                 if (l == 0)
                     tail_smooth<T, 4>(g, q0, e[0], colour, omega);
@@ -3374,12 +3373,12 @@ k_coarse_tail(const Grid *grids, const int *roots, const int *active, int *fail,
     for (int c = threadIdx.x; c < nc; c += kTailBlock)
         r[c] = (T)y[c];
     __syncthreads();
-    // up: prolongate, nu2 post-sweeps (black then red)
+    // up: prolongate, the level's post-sweeps (black then red)
     for (int l = nd - 1; l >= 0; --l) {
         const Grid &g = grids[lv[l]];
         tail_prolong<T>(g, grids[lv[l + 1]], e[l], l + 1 == nd ? r : e[l + 1]);
         __syncthreads();
-        for (int s = 0; s < nu2; ++s)
+        for (int s = 0; s < g.nu_post; ++s)
             for (int colour = 1; colour >= 0; --colour) {
                 if (l == 0)
                     tail_smooth<T, 4>(g, q0, e[0], colour, omega);
@@ -3738,11 +3737,11 @@ void launch_coarse_factor(hipStream_t s, const Grid *grids, const int *ids, int 
 }
 template <typename T>
 void launch_tail(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
-                 int *fail, int nu1, int nu2, double omega, int lds_bytes)
+                 int *fail, double omega, int lds_bytes)
 {
     if (count > 0)
         hipLaunchKernelGGL(k_coarse_tail<T>, dim3(count), dim3(kTailBlock), lds_bytes, s, grids,
-                           roots, active, fail, nu1, nu2, (T)omega);
+                           roots, active, fail, (T)omega);
 }
 
 long long tail_lds_need(long long nc, long long bw, long long deep_cells, long long scratch_cells,
@@ -3758,11 +3757,11 @@ int tail_max_low() { return kTailMaxLow; }
 
 template <typename T>
 void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, const int *active,
-                 int nu, double omega, bool down)
+                 double omega, bool down)
 {
     if (count > 0)
         hipLaunchKernelGGL(down ? k_deep_down<T> : k_deep_up<T>, dim3(count), dim3(kDeepBlock), 0, s,
-                           grids, roots, active, nu, (T)omega);
+                           grids, roots, active, (T)omega);
 }
 
 #define FLD_INSTANTIATE(T)                                                                       \
@@ -3776,10 +3775,10 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
     template void launch_mean8_sa<T>(hipStream_t, const Grid *, const Task *, int);              \
     template void launch_coarse_solve<T>(hipStream_t, const Grid *, const int *, int,            \
                                          const int *, int *, int, int);                          \
-    template void launch_deep<T>(hipStream_t, const Grid *, const int *, int, const int *, int,  \
+    template void launch_deep<T>(hipStream_t, const Grid *, const int *, int, const int *,       \
                                  double, bool);                                                  \
     template void launch_tail<T>(hipStream_t, const Grid *, const int *, int, const int *, int *,  \
-                                 int, int, double, int);                                         \
+                                 double, int);                                                   \
     template void launch_coarse_factor<T>(hipStream_t, const Grid *, const int *, int,           \
                                           const int *, int *, int);                              \
     template void launch_smooth_rb<T>(hipStream_t, const Grid *, const LrTile *, int,            \

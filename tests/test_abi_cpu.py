@@ -55,6 +55,9 @@ def test_default_options():
     ({"fuse_rb": -1}, (8, 8, 8), 0.1),
     ({"aa_m": 17}, (8, 8, 8), 0.1),
     ({"aa_reg": -1.0}, (8, 8, 8), 0.1),
+    ({"nu_coarse": 65}, (8, 8, 8), 0.1),
+    ({"nu_coarse": -1}, (8, 8, 8), 0.1),
+    ({"nu_coarse": 8, "coarse_from": 0}, (8, 8, 8), 0.1),
 ])
 def test_create_rejects_invalid_arguments(kw, dims, h):
     o = F.fld_default_options(**kw)

@@ -434,6 +434,30 @@ def test_anderson_reaches_the_brute_force_fixed_point(oracle_mod, case):
     assert np.linalg.norm(aa.phi - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
+def test_coarse_level_sweeps_change_the_path_not_the_fixed_point(oracle_mod):
+    # nu_coarse sweeps on the coarse levels (the 8^3 level of a 16^3 grid; the
+    # 4^3 level is solved) change the V-cycle; the multigrid still lands on the
+    # brute-force Picard fixed point
+    st, al, Q, h = media.config("cloud128", n=16)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="lp")
+    ref = picard_direct(oracle_mod, prob, h)
+    base = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000)
+    # nu_coarse equal to nu1 = nu2 is the same cycle, bit for bit
+    same = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000, nu_coarse=2,
+                            coarse_from=1)
+    np.testing.assert_array_equal(same.phi, base.phi)
+    for m in (1, 8):
+        r = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000, nu_coarse=m,
+                             coarse_from=1)
+        assert r.status == "converged"
+        assert np.linalg.norm(r.phi - ref) <= 1e-10 * np.linalg.norm(ref)
+        assert r.iterations != base.iterations or not np.array_equal(r.history, base.history)
+    # from level 2 on there is nothing to smooth on this grid: the default cycle
+    r = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000, nu_coarse=8,
+                         coarse_from=2)
+    np.testing.assert_array_equal(r.phi, base.phi)
+
+
 def test_anderson_and_conjugate_gradient_share_the_fixed_point(oracle_mod):
     # the 256^3 generator at 32^3 has vacuum clusters (deflation active) and
     # residual growth in the first iterations (restarts active)
