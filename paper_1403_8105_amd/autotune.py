@@ -69,7 +69,8 @@ AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.
                 (6, 6, 1.15), (4, 4, 1.25)]
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 AA_NESTED = [3e-3, 1e-2, 3e-2, 1e-1]   # grid sequencing with the chosen window
-COARSE_SWEEPS = [(8, 2), (12, 2), (16, 2), (24, 2), (12, 1), (16, 1), (16, 3), (24, 3)]
+COARSE_SWEEPS = [(8, 2), (12, 2), (16, 2), (24, 2), (32, 2), (12, 1), (16, 1), (16, 3), (24, 3),
+                 (32, 3)]
 PASSES = [(0, 0), (1, 0), (0, 1), (1, 1)]   # (fuse_rb, fuse_lr)
 
 
