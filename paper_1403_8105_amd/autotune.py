@@ -23,9 +23,10 @@ in device memory:
    changes with the outer step), the regularisation, and how far the coarser
    problem is solved first.  Starting from the cached entry it runs alone.
    ``coarse`` then tries extra smoothing sweeps on the coarse levels
-   (``nu_coarse`` from level ``coarse_from`` on) for the winner and, with an
-   Anderson window, the windows again; with ``refine`` it starts from the
-   cached entry and runs alone.
+   (``nu_coarse`` from level ``coarse_from`` on) for the winner, then the
+   sweeps on the levels above them (``nu1`` = ``nu2``) and, with an Anderson
+   window, the windows again; with ``refine`` it starts from the cached entry
+   and runs alone.
 4. Pass forms, with the winner's options: the finest level's red and black
    half-sweeps fused into single LDS-tiled sweeps (``fuse_rb``) and the
    limiter and residual fused into one pass (``fuse_lr``), each on or off.
@@ -70,7 +71,8 @@ AA_SCHEDULES = [(4, 4, 1.15), (3, 3, 1.15), (2, 2, 1.15), (3, 3, 1.0), (2, 2, 1.
 AA_SCALES = [1.4, 1.6, 1.8, 2.0]
 AA_NESTED = [3e-3, 1e-2, 3e-2, 1e-1]   # grid sequencing with the chosen window
 COARSE_SWEEPS = [(8, 2), (12, 2), (16, 2), (24, 2), (32, 2), (12, 1), (16, 1), (16, 3), (24, 3),
-                 (32, 3)]
+                 (32, 3), (48, 3)]
+FINE_SWEEPS = [2, 3, 4, 5]      # nu1 = nu2 on the finest levels, retried with the coarse sweeps
 PASSES = [(0, 0), (1, 0), (0, 1), (1, 1)]   # (fuse_rb, fuse_lr)
 
 
@@ -303,10 +305,17 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
                                           b4["restart_growth"], b4["corr_scale"], nt, b4["aa_m"],
                                           b4.get("aa_reg", 1e-10)), best)
     if coarse and best is not None:
-        # extra sweeps on the coarse levels, then (with a window) the windows again
+        # extra sweeps on the coarse levels, the sweeps above them, then (with
+        # a window) the windows again
         b5 = best
         for nc, cf in COARSE_SWEEPS:
-            best = better(again(b5, nc=nc, cf=cf), best)
+            if (nc, cf) != (b5.get("nu_coarse", 0), b5.get("coarse_from", 2)):
+                best = better(again(b5, nc=nc, cf=cf), best)
+        b7 = best
+        if b7.get("nu_coarse"):
+            for nf in FINE_SWEEPS:
+                if (nf, nf) != (b7["nu1"], b7["nu2"]):
+                    best = better(again(b7, nu1=nf, nu2=nf), best)
         if best is not b5 and best.get("aa_m"):
             b6 = best
             for m in AA_WINDOWS:
@@ -463,7 +472,13 @@ def tune_batch(precision: str = "mixed", limiter: str = "lp", tol: float = 1e-6,
     if coarse:
         b5 = best
         for nc, cf in COARSE_SWEEPS:
-            best = better(again(b5, nc=nc, cf=cf), best)
+            if (nc, cf) != (b5.get("nu_coarse", 0), b5.get("coarse_from", 2)):
+                best = better(again(b5, nc=nc, cf=cf), best)
+        b7 = best
+        if b7.get("nu_coarse"):
+            for nf in FINE_SWEEPS:
+                if (nf, nf) != (b7["nu1"], b7["nu2"]):
+                    best = better(again(b7, nu1=nf, nu2=nf), best)
         if best is not b5 and best.get("aa_m"):
             b6 = best
             for m in AA_WINDOWS:
