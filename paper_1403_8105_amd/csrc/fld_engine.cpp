@@ -112,6 +112,8 @@ struct fld_engine_impl {
     int *d_lr_range = nullptr;
     double *d_lrpart = nullptr;
     DevList mid[kMaxLevels], rest[kMaxLevels], gal[kMaxLevels];
+    int mid_cells[kMaxLevels] = {};   // cells per smoothing task of each level
+    std::vector<Grid> h_grids;        // host copy of the grid table (parity 0)
     DevList coarse_cells[kMaxLevels];   // every cell of level l+1 (deep levels included)
     int *d_coarse_ids = nullptr, *d_deep_roots = nullptr;   // coarsest grids / deep roots
     int n_coarse = 0, n_deep = 0;
@@ -648,6 +650,7 @@ struct fld_engine_impl {
                 grids[1].push_back(g);
             }
         }
+        h_grids = grids[0];
         ngrids = (int)grids[0].size();
         if (fuse_rb) {
             std::vector<LrTile> rt;
@@ -750,6 +753,7 @@ struct fld_engine_impl {
                     ng += (long long)(C.nx + 1) * (C.ny + 1) * face_zstride(C.nz);
                 }
             const int tm = l == 0 ? opt.task_cells0 : coarse_task(nm, 512);
+            mid_cells[l] = tm;
             const int tr = coarse_task(nr, 256), tg = coarse_task(ng, 256);
             for (int p = 0; p < nprob; ++p) {
                 const Prob &P = probs[p];
@@ -1063,6 +1067,13 @@ struct fld_engine_impl {
     template <typename T>
     void smooth(Grid *G, int l, int colour)
     {
+        if (l > 0 && nprob == 1) {
+            // one problem: the coarse level by value, no task or activity loads
+            // (a solve stops launching once its only problem has converged)
+            launch_smooth_one<T>(stream, h_grids[probs[0].gid0 + l], mid_cells[l], colour,
+                                 opt.omega_s);
+            return;
+        }
         hipEvent_t a = l == 0 ? tic() : nullptr;
         launch_smooth<T>(stream, G, mid[l].d, mid[l].n, d_active, colour, opt.omega_s, l == 0);
         if (l == 0)

@@ -215,6 +215,12 @@ void launch_zero(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks
 template <typename T>
 void launch_smooth(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
                    const int *active, int colour, double omega, bool finest);
+// One half-sweep of a coarse (not the finest) level of a single problem, the
+// level passed by value (no task list, no activity mask): block b smooths
+// cells [b * task_cells, (b + 1) * task_cells); task_cells a multiple of 8.
+// The same result as launch_smooth over that level's tasks.
+template <typename T>
+void launch_smooth_one(hipStream_t s, const Grid &g, int task_cells, int colour, double omega);
 template <typename T>
 void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
                      const int *active, int sp);

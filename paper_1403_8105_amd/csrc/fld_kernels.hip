@@ -1959,14 +1959,9 @@ k_zero(const Grid *grids, const Task *tasks, int ntasks, const int *active)
 // face coefficients formed on the fly; FINE) and the coarse levels (stored
 // Galerkin faces) are separate kernels, each compiled with its own paths only.
 template <typename T, bool FINE>
-__device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *tasks, int ntasks,
-                                             const int *active, int colour, T omega)
+__device__ __forceinline__ void smooth_task(const Grid &g, const Task tk, int colour, T omega)
 {
-    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
-        const Task tk = tasks[t];
-        const Grid &g = grids[tk.grid];
-        if (active && !active[g.prob])
-            continue;
+    {
         T *e = (T *)g.e;
         const Dec dec(g.ny, g.nz);
         const int npairs = tk.count >> 1;
@@ -2197,6 +2192,19 @@ __device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *task
     }
 }
 
+template <typename T, bool FINE>
+__device__ __forceinline__ void smooth_tasks(const Grid *grids, const Task *tasks, int ntasks,
+                                             const int *active, int colour, T omega)
+{
+    for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+        const Task tk = tasks[t];
+        const Grid &g = grids[tk.grid];
+        if (active && !active[g.prob])
+            continue;
+        smooth_task<T, FINE>(g, tk, colour, omega);
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_smooth_fine(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour,
@@ -2210,6 +2218,19 @@ __global__ void __launch_bounds__(kBlock)
 k_smooth(const Grid *grids, const Task *tasks, int ntasks, const int *active, int colour, T omega)
 {
     smooth_tasks<T, false>(grids, tasks, ntasks, active, colour, omega);
+}
+
+// The same half-sweep of one coarse level of a single problem, the level
+// passed by value and block b taking cells [b * task_cells, ...): no task,
+// grid or activity record to fetch before the cells' own loads, which is most
+// of a small level's launch time.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_smooth_one(Grid g, int task_cells, int colour, T omega)
+{
+    const long long start = (long long)blockIdx.x * task_cells;
+    const Task tk{0, (int)(g.n - start < task_cells ? g.n - start : task_cells), start};
+    smooth_task<T, false>(g, tk, colour, omega);
 }
 
 // One red-black sweep of the finest level in a single pass, out of place
@@ -3678,6 +3699,15 @@ void launch_smooth(hipStream_t s, const Grid *grids, const Task *tasks, int ntas
 }
 
 template <typename T>
+void launch_smooth_one(hipStream_t s, const Grid &g, int task_cells, int colour, double omega)
+{
+    const long long blocks = (g.n + task_cells - 1) / task_cells;
+    if (blocks > 0)
+        hipLaunchKernelGGL(k_smooth_one<T>, dim3((unsigned)blocks), dim3(kBlock), 0, s, g,
+                           task_cells, colour, (T)omega);
+}
+
+template <typename T>
 void launch_restrict(hipStream_t s, const Grid *grids, const Task *tasks, int ntasks,
                      const int *active, int sp)
 {
@@ -3768,6 +3798,7 @@ void launch_deep(hipStream_t s, const Grid *grids, const int *roots, int count, 
     template void launch_zero<T>(hipStream_t, const Grid *, const Task *, int, const int *);     \
     template void launch_smooth<T>(hipStream_t, const Grid *, const Task *, int, const int *,    \
                                    int, double, bool);                                           \
+    template void launch_smooth_one<T>(hipStream_t, const Grid &, int, int, double);             \
     template void launch_restrict<T>(hipStream_t, const Grid *, const Task *, int, const int *, int); \
     template void launch_prolong<T>(hipStream_t, const Grid *, const Task *, int, const int *, int,  \
                                     double);  \
