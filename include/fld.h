@@ -170,6 +170,10 @@ typedef struct fld_options {
                              latency-bound), and a better coarse correction saves outer
                              iterations                                                    */
     int coarse_from;      /* first level that nu_coarse applies to, >= 1 (default 2)      */
+    int nested_inherit;   /* grid sequencing: 1 gives the coarse solve this solve's schedule
+                             (nu1, nu2, omega_s, corr_scale, restart_growth, aa_m, aa_reg,
+                             and nu_coarse from level coarse_from - 1, at least 1: the same
+                             level sizes); 0 (default) the default schedule               */
 } fld_options;
 
 typedef struct fld_report {

@@ -368,20 +368,27 @@ def nested_problem(prob: Problem) -> Problem:
 
 
 def solve(prob: Problem, method: str = "mg", phi=None, D=None, hist_cap: int = 100000,
-          nested_tol: float = 0.0, **kw):
+          nested_tol: float = 0.0, nested_inherit: bool = False, **kw):
     """Run Algorithm 1 (method='alg1') or Picard-multigrid (method='mg').
 
     phi/D: start state (default: the paper's initialisation).  Returns the
     final state and the relative-residual history (one entry per check).
     nested_tol > 0 (multigrid from the paper's initialisation): grid
     sequencing -- first solve nested_problem(prob) with the default schedule
-    to nested_tol (at most 10000 iterations) and start from its fluence,
-    constant over each 2x2x2 block;
+    (nested_inherit: with this solve's schedule, the coarse-level sweeps one
+    level up) to nested_tol (at most 10000 iterations) and start from its
+    fluence, constant over each 2x2x2 block;
     the result's ``nested_iterations`` counts the coarse iterations.
     """
     if nested_tol > 0.0 and phi is None and method == "mg":
         coarse = nested_problem(prob)
         ck = {k: kw[k] for k in ("deflate_tau", "max_coarsest") if k in kw}
+        if nested_inherit:
+            ck.update({k: kw[k] for k in ("nu1", "nu2", "omega_s", "corr_scale",
+                                          "restart_growth", "aa_m", "aa_reg", "nu_coarse")
+                       if k in kw})
+            if "nu_coarse" in kw:
+                ck["coarse_from"] = max(1, kw.get("coarse_from", 2) - 1)
         rc = solve(coarse, method="mg", tol=nested_tol, max_iters=10000, **ck)
         start = rc.phi.repeat(2, axis=0).repeat(2, axis=1).repeat(2, axis=2)
         if rc.status == "diverged":

@@ -41,7 +41,7 @@ class fld_options(C.Structure):
                 ("deep_cells", C.c_int), ("nested_tol", C.c_double), ("aa_m", C.c_int),
                 ("aa_reg", C.c_double), ("fuse_lr", C.c_int),
                 ("fuse_rb", C.c_int), ("debug_nan_iter", C.c_int),
-                ("nu_coarse", C.c_int), ("coarse_from", C.c_int)]
+                ("nu_coarse", C.c_int), ("coarse_from", C.c_int), ("nested_inherit", C.c_int)]
 
 
 class fld_report(C.Structure):

@@ -1542,6 +1542,7 @@ fld_status validate_options(const fld_options *o, std::string &err)
     if (o->debug_nan_iter < 0) { err = "debug_nan_iter must be >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->nu_coarse < 0 || o->nu_coarse > 64) { err = "nu_coarse must lie in [0,64]"; return FLD_ERR_INVALID_ARGUMENT; }
     if (o->coarse_from < 1) { err = "coarse_from must be >= 1"; return FLD_ERR_INVALID_ARGUMENT; }
+    if (o->nested_inherit != 0 && o->nested_inherit != 1) { err = "nested_inherit must be 0 or 1"; return FLD_ERR_INVALID_ARGUMENT; }
     if (!(o->aa_reg >= 0.0 && std::isfinite(o->aa_reg))) { err = "aa_reg must be finite and >= 0"; return FLD_ERR_INVALID_ARGUMENT; }
     return FLD_OK;
 }
@@ -1660,6 +1661,7 @@ fld_status fld_default_options(fld_options *o)
     o->debug_nan_iter = 0;
     o->nu_coarse = 0;
     o->coarse_from = 2;
+    o->nested_inherit = 0;
     return FLD_OK;
 }
 
@@ -1688,6 +1690,19 @@ static fld_options nested_options(const fld_options *o)
     co.deflate_tau = o->deflate_tau;
     co.graph = o->graph;
     co.colour_split = o->colour_split;
+    if (o->nested_inherit) {
+        // the fine solve's schedule; the coarse grid's level l is the fine
+        // grid's level l + 1
+        co.nu1 = o->nu1;
+        co.nu2 = o->nu2;
+        co.omega_s = o->omega_s;
+        co.corr_scale = o->corr_scale;
+        co.restart_growth = o->restart_growth;
+        co.aa_m = o->aa_m;
+        co.aa_reg = o->aa_reg;
+        co.nu_coarse = o->nu_coarse;
+        co.coarse_from = std::max(1, o->coarse_from - 1);
+    }
     return co;
 }
 

@@ -58,6 +58,7 @@ def test_default_options():
     ({"nu_coarse": 65}, (8, 8, 8), 0.1),
     ({"nu_coarse": -1}, (8, 8, 8), 0.1),
     ({"nu_coarse": 8, "coarse_from": 0}, (8, 8, 8), 0.1),
+    ({"nested_inherit": 2}, (8, 8, 8), 0.1),
 ])
 def test_create_rejects_invalid_arguments(kw, dims, h):
     o = F.fld_default_options(**kw)

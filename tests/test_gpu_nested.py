@@ -40,6 +40,24 @@ def test_nested_fp64_iterate_parity(shape):
         assert rel_l2(phi, ref.phi) <= 1e-10, k
 
 
+def test_nested_inherit_fp64_iterate_parity():
+    # the coarse solve with the fine solve's schedule (Anderson window, sweeps,
+    # coarse-level sweeps one level up) against the oracle's
+    st, al, Q, h = media.cloud_medium((32, 32, 32), 4, 200.0, 0.4, 0.99, 21)
+    prob = oracle.setup(st, al, Q, h)
+    kw = dict(nu1=3, nu2=3, omega_s=1.15, corr_scale=1.4, aa_m=4, nu_coarse=6, coarse_from=2)
+    plain = oracle.solve(prob, method="mg", tol=0.0, max_iters=1, nested_tol=1e-3, **kw)
+    for k in (1, 6):
+        ref = oracle.solve(prob, method="mg", tol=0.0, max_iters=k, nested_tol=1e-3,
+                           nested_inherit=True, **kw)
+        phi, rep = solve_gpu(st, al, Q, h, tol=0.0, max_iters=k, nested_tol=1e-3,
+                             nested_inherit=1, **kw)
+        assert rep["nested_iterations"] == ref.nested_iterations > 0
+        assert ref.nested_iterations != plain.nested_iterations
+        assert rep["iterations"] == ref.iterations == k
+        assert rel_l2(phi, ref.phi) <= 1e-10, k
+
+
 def test_nested_mixed_reaches_the_fp64_fixed_point():
     st, al, Q, h = media.config("cloud128", n=32)
     prob = oracle.setup(st, al, Q, h)
