@@ -131,6 +131,18 @@ def _apply_passes(opts: dict, pass_ms: dict) -> dict:
     return opts
 
 
+def _device_inputs(sigma_t, albedo, Q):
+    """The medium in device memory: (tensors to keep alive, the three input
+    pointers, the fluence buffer's pointer, the stream)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (sigma_t, albedo, Q)]
+    d_phi = torch.empty_like(d[0])
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    return d + [d_phi], [t.data_ptr() for t in d], d_phi.data_ptr(), stream
+
+
 def _solve_ms(F, st, h, dev_inputs, d_phi, stream, opts):
     """One device solve; returns (wall ms, report)."""
     import torch
@@ -159,15 +171,10 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     ``anderson`` adds phase 3 (with ``refine``: phase 3 alone).  ``tol_key``
     stores the entry under a key that names ``tol``; ``refine`` then starts
     from that entry or, if there is none yet, from the grid's own."""
-    import torch
-
     import paper_1403_8105_amd as F
 
-    dev = torch.device("cuda:0")
-    d = [torch.from_numpy(a).to(dev) for a in (sigma_t, albedo, Q)]
-    d_phi = torch.empty_like(d[0])
-    stream = torch.cuda.current_stream(dev).cuda_stream
-    ptrs = [t.data_ptr() for t in d]
+    # keep: the device tensors, alive until the search ends
+    keep, ptrs, phi_ptr, stream = _device_inputs(sigma_t, albedo, Q)
     base = dict(precision=precision, limiter=limiter)
     even = all(x % 2 == 0 for x in sigma_t.shape)
     key = cache_key(device_arch(), sigma_t.shape, precision, limiter, tol if tol_key else None)
@@ -182,7 +189,7 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         entry = cache0.get(key)
         if not entry:
             raise RuntimeError(f"autotune: --passes-only needs a cached entry for {key}")
-        pass_ms = _pass_forms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream,
+        pass_ms = _pass_forms(F, sigma_t, h, ptrs, phi_ptr, stream,
                               dict(base, **entry["options"]), probe_iters, log)
         entry = dict(entry, options=_apply_passes(entry["options"], pass_ms),
                      pass_ms_per_iteration={f"{a},{b}": v for (a, b), v in pass_ms.items()})
@@ -202,8 +209,8 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
     else:
         for tc0, cb in SHAPES:
             o = dict(base, tol=0.0, max_iters=probe_iters, task_cells0=tc0, coarse_blocks=cb)
-            _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)      # warm
-            ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
+            _solve_ms(F, sigma_t, h, ptrs, phi_ptr, stream, o)      # warm
+            ms, rep = _solve_ms(F, sigma_t, h, ptrs, phi_ptr, stream, o)
             shape_ms[(tc0, cb)] = ms / max(rep["iterations"], 1)
             log(f"autotune: task_cells0={tc0} coarse_blocks={cb}: "
                 f"{shape_ms[(tc0, cb)]:.4f} ms/it")
@@ -217,7 +224,7 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         o = dict(base, tol=tol, max_iters=max_iters, task_cells0=tc0, coarse_blocks=cb,
                  nu1=nu1, nu2=nu2, omega_s=ws, restart_growth=gr, corr_scale=sc, nested_tol=nt,
                  aa_m=aa, aa_reg=reg, nu_coarse=nc, coarse_from=cf)
-        ms, rep = _solve_ms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, o)
+        ms, rep = _solve_ms(F, sigma_t, h, ptrs, phi_ptr, stream, o)
         ok = rep["status"] == F.FLD_OK
         results.append({"nu1": nu1, "nu2": nu2, "omega_s": ws, "restart_growth": gr,
                         "corr_scale": sc, "nested_tol": nt, "aa_m": aa, "aa_reg": reg,
@@ -336,7 +343,7 @@ def tune(sigma_t, albedo, Q, h, precision: str = "mixed", limiter: str = "lp", t
         opts["nu_coarse"] = best["nu_coarse"]
         opts["coarse_from"] = best["coarse_from"]
     # phase 4: pass forms with the winner's options
-    pass_ms = _pass_forms(F, sigma_t, h, ptrs, d_phi.data_ptr(), stream, dict(base, **opts),
+    pass_ms = _pass_forms(F, sigma_t, h, ptrs, phi_ptr, stream, dict(base, **opts),
                           probe_iters, log)
     opts = _apply_passes(opts, pass_ms)
     entry = {
