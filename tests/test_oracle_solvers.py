@@ -458,6 +458,20 @@ def test_coarse_level_sweeps_change_the_path_not_the_fixed_point(oracle_mod):
     np.testing.assert_array_equal(r.phi, base.phi)
 
 
+def test_inherited_grid_sequencing_keeps_the_fixed_point(oracle_mod):
+    # the coarse solve of grid sequencing with the fine solve's schedule
+    # (nested_inherit) takes another path to the same fixed point
+    st, al, Q, h = media.config("cloud128", n=16)
+    prob = oracle_mod.setup(st, al, Q, h, limiter="lp")
+    kw = dict(nu1=3, nu2=3, omega_s=1.15, corr_scale=1.4, aa_m=4, nu_coarse=6, coarse_from=2)
+    plain = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000, nested_tol=1e-3, **kw)
+    inh = oracle_mod.solve(prob, method="mg", tol=1e-12, max_iters=2000, nested_tol=1e-3,
+                           nested_inherit=True, **kw)
+    assert plain.status == inh.status == "converged"
+    assert inh.nested_iterations != plain.nested_iterations
+    assert np.linalg.norm(inh.phi - plain.phi) <= 1e-10 * np.linalg.norm(plain.phi)
+
+
 def test_anderson_and_conjugate_gradient_share_the_fixed_point(oracle_mod):
     # the 256^3 generator at 32^3 has vacuum clusters (deflation active) and
     # residual growth in the first iterations (restarts active)
